@@ -1,0 +1,155 @@
+/*
+ * bc.h -- exact (p,q)-biclique counting on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section II-A, Definition 1 and the problem statement): given a
+ * bipartite graph G = (U, V, E) and two integers p, q, return the number of
+ * pairs (L, R) with L a p-subset of U, R a q-subset of V and every (u, v) in
+ * L x R an edge of E.  Equivalently, the sum over p-subsets L of U of
+ * C(|common neighbours of L|, q) -- the leaf rule of the Basic model
+ * (Section III-A), which is what the device path evaluates.
+ *
+ * Plain C99 ABI: fixed-width integers and plain pointers only.  Every call
+ * returns a bc_status (0 = BC_OK, negative = error); nothing throws across
+ * the boundary.  On error no output argument is written, and
+ * bc_last_error() returns a detail message for the calling thread.
+ *
+ * Counts are exact unsigned 128-bit integers (count = hi * 2^64 + lo).  If the
+ * true count does not fit in 128 bits the call fails with BC_E_OVERFLOW.
+ * No floating point takes part in any count.
+ */
+#ifndef BC_H
+#define BC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bc_status;
+enum {
+    BC_OK = 0,
+    BC_E_INVALID_ARG = -1,   /* NULL pointer, p or q outside 1..32, bad option value */
+    BC_E_BAD_CSR = -2,       /* indptr not a prefix array, id out of range, duplicate edge */
+    BC_E_INCONSISTENT = -3,  /* the U-side and V-side CSRs are not transposes */
+    BC_E_OOM = -4,           /* host or device allocation failed */
+    BC_E_DEVICE = -5,        /* a HIP runtime error; the HIP message is in bc_last_error() */
+    BC_E_OVERFLOW = -6,      /* the count needs more than 128 bits */
+    BC_E_REJECTED = -7,      /* server: query refused by admission control */
+    BC_E_TIMEOUT = -8,       /* server: deadline passed before the query ran */
+    BC_E_CANCELLED = -9,     /* server: shut down before the query ran */
+    BC_E_PENDING = -10,      /* server: non-blocking poll, result not ready yet */
+    BC_E_NOT_FOUND = -11     /* server: unknown ticket or graph id */
+};
+
+typedef struct { uint64_t lo, hi; } bc_u128;
+
+/* One side of the graph in CSR form, in HOST memory.  Row r lists the ids
+ * (in [0, n_cols)) of the other side adjacent to vertex r; rows may be
+ * unsorted, duplicates are rejected.  indptr has n_rows + 1 nondecreasing
+ * entries with indptr[0] == 0 and indptr[n_rows] == nnz. */
+typedef struct {
+    uint64_t n_rows, n_cols, nnz;
+    const uint64_t *indptr;
+    const uint32_t *indices;
+} bc_csr;
+
+typedef struct bc_graph bc_graph;   /* opaque; immutable after bc_build */
+
+/* Anchor: the side that L is drawn from.  The count never depends on it. */
+enum { BC_ANCHOR_AUTO = -1, BC_ANCHOR_U = 0, BC_ANCHOR_V = 1 };
+
+/* Options.  Pass NULL for all defaults.  No field changes any count. */
+typedef struct {
+    uint32_t struct_size;      /* sizeof(bc_opts), for forward compatibility */
+    void *stream;              /* hipStream_t to run on; NULL = the library's own stream */
+    int32_t anchor;            /* BC_ANCHOR_AUTO / _U / _V */
+    uint32_t lds_words;        /* per-wavefront LDS budget in 64-bit words; 0 = default */
+    uint32_t waves_per_cu;     /* persistent-grid occupancy target; 0 = default */
+    uint32_t instrument;       /* nonzero: fill the work counters of bc_stats */
+} bc_opts;
+
+/* Timings (milliseconds, measured with HIP events on the stream) and work
+ * counters of one count. */
+typedef struct {
+    double ms_total, ms_candidates, ms_plan, ms_rows, ms_enumerate;
+    int32_t anchor;            /* side actually used */
+    uint64_t roots;            /* roots of the anchor side visited */
+    uint64_t roots_active;     /* roots that own at least one task */
+    uint64_t tasks;            /* (root, second vertex) tasks enumerated */
+    uint64_t candidate_edges;  /* oriented 2-hop pairs sharing >= q (or p) neighbours */
+    uint64_t row_words;        /* 64-bit words of per-root candidate bitmaps */
+    uint64_t pair_ops;         /* instrumented: 64-bit word ANDs+popcounts of the fused leaf pairs */
+    uint64_t filter_ops;       /* instrumented: 64-bit word ANDs+popcounts of the child filters */
+} bc_stats;
+
+/*
+ * bc_build -- validate a bipartite graph and copy it to the device.
+ *
+ * U lists N(u) for every u in U (n_rows = |U|, n_cols = |V|); V lists N(v)
+ * for every v in V and must be the exact transpose of U (BC_E_INCONSISTENT
+ * otherwise).  Rows are sorted and each side is relabelled by degree order
+ * (ascending degree, ties by original id); a vertex's position in that order
+ * is its "rank", which fixes the orientation of the search (vertex priority,
+ * Section III-B, Definition 2 with degree as the key).  Both CSR sides are
+ * then copied to device memory on opts->stream.  The caller keeps ownership
+ * of its arrays; nothing refers to them after return.  *out receives a graph
+ * that owns its device memory until bc_free.
+ */
+bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *opts, bc_graph **out);
+
+/* Releases a graph and its device memory.  NULL is ignored. */
+void bc_free(bc_graph *g);
+
+/* Sizes of a built graph. */
+bc_status bc_graph_info(const bc_graph *g, uint64_t *n_u, uint64_t *n_v, uint64_t *n_edges);
+
+/*
+ * rank_of[x] for every vertex x of one side (0 = U, 1 = V), in original ids:
+ * the rank that orients the search.  rank_of must hold n entries.
+ */
+bc_status bc_ranks(const bc_graph *g, int32_t side, uint32_t *rank_of);
+
+/*
+ * bc_count -- number of (p,q)-bicliques of g, 1 <= p, q <= 32.
+ *
+ * Runs entirely on the device (Algorithm 1 restated for CDNA4): per-root
+ * 2-hop candidate collection, bitmap rows of the common neighbours,
+ * enumeration with AND + popcount, each leaf adding C(|S|, q) from an exact
+ * table.  p > |U| or q > |V| gives 0.  The call returns when the count is on
+ * the host.  *st (nullable) receives timings and counters.
+ */
+bc_status bc_count(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts,
+                   bc_u128 *out, bc_stats *st);
+
+/*
+ * bc_count_roots -- the part of the count whose lowest-ranked L vertex has
+ * rank in [rank_lo, rank_hi) on the given anchor side (BC_ANCHOR_U or _V;
+ * AUTO is rejected).  Disjoint rank ranges give partial counts that add up
+ * exactly to bc_count; with a one-rank range it is the per-root count.
+ */
+bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor,
+                         uint64_t rank_lo, uint64_t rank_hi, const bc_opts *opts,
+                         bc_u128 *out, bc_stats *st);
+
+/*
+ * bc_count_batch -- n independent counts (graphs[i], p[i], q[i]) in one set
+ * of persistent launches sharing one task queue.  out[i] and item_status[i]
+ * receive each result; the call itself fails only on argument or device
+ * errors.  Every out[i] equals what bc_count would return.
+ */
+bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q,
+                         size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status);
+
+/* Human-readable name of a status code (static storage). */
+const char *bc_status_string(bc_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *bc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_H */

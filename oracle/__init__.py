@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OK, E_ARG, E_CSR, E_OVERFLOW, E_OOM = 0, -1, -2, -3, -4
+OK, E_ARG, E_CSR, E_OVERFLOW, E_OOM, E_BUDGET = 0, -1, -2, -3, -4, -5
 ORDER_ID, ORDER_DEGREE, ORDER_TWO_HOP = 0, 1, 2
 
 
@@ -49,7 +49,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
         lib.oracle_count.argtypes = [U64, U64, P, P, U32, U32, I, I, U64, U64, I, P, P, P]
-        lib.oracle_count_ranks.argtypes = [U64, U64, P, P, U32, U32, I, P, U64, I, P, P]
+        lib.oracle_count_ranks.argtypes = [U64, U64, P, P, U32, U32, I, P, U64, I, U64, P, P, P]
         lib.oracle_order.argtypes = [U64, U64, P, P, I, U32, P]
         lib.oracle_basic_sets.argtypes = [U64, U64, P, P, U32, P, U32, P, P, P, P]
         lib.oracle_htb_encode.argtypes = [P, U32, U32, P, P, P]
@@ -106,8 +106,11 @@ def count(g, p, q, *, anchor="U", **kw):
     return count_csr(g.n_v, g.n_u, g.indptr_v, g.indices_v, q, p, **kw)
 
 
-def count_ranks(g, p, q, ranks, *, anchor="U", order_key=ORDER_DEGREE, threads=None):
-    """Per-root counts for the roots of the given ranks (list of python ints)."""
+def count_ranks(g, p, q, ranks, *, anchor="U", order_key=ORDER_DEGREE, threads=None, max_nodes=0):
+    """Per-root counts for the roots of the given ranks (list of python ints).
+
+    With max_nodes > 0, a root needing more intersections than that is not
+    computed and its entry is None."""
     lib = _load()
     if anchor == "U":
         n_u, n_v, ip, ix, pp, qq = g.n_u, g.n_v, g.indptr_u, g.indices_u, p, q
@@ -117,12 +120,14 @@ def count_ranks(g, p, q, ranks, *, anchor="U", order_key=ORDER_DEGREE, threads=N
     r = np.ascontiguousarray(ranks, dtype=np.uint64)
     lo = np.zeros(max(1, r.size), dtype=np.uint64)
     hi = np.zeros(max(1, r.size), dtype=np.uint64)
+    st = np.zeros(max(1, r.size), dtype=np.int32)
     rc = lib.oracle_count_ranks(n_u, n_v, _ptr(ip), _ptr(ix), pp, qq, order_key,
                                 _ptr(r) if r.size else None, r.size,
-                                threads or default_threads(), _ptr(lo), _ptr(hi))
+                                threads or default_threads(), max_nodes, _ptr(lo), _ptr(hi), _ptr(st))
     if rc != OK:
         raise OracleError(rc, "count_ranks")
-    return [(int(h) << 64) | int(l) for l, h in zip(lo[:r.size], hi[:r.size])]
+    return [((int(h) << 64) | int(l)) if s == OK else None
+            for l, h, s in zip(lo[:r.size], hi[:r.size], st[:r.size])]
 
 
 def order(n_u, n_v, indptr_u, indices_u, order_key, q=1):

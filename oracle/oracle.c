@@ -51,6 +51,7 @@ enum {
     OR_E_CSR = -2,
     OR_E_OVERFLOW = -3,
     OR_E_OOM = -4,
+    OR_E_BUDGET = -5,   /* a root needed more intersections than allowed */
 };
 
 /* ------------------------------------------------------------------ */
@@ -285,6 +286,8 @@ typedef struct {
     const uint64_t *rank_list;   /* if non-NULL: count these ranks one by one */
     uint64_t n_list;
     u128 *per_list;              /* per-entry counts for rank_list */
+    int32_t *per_status;         /* per-entry status for rank_list */
+    uint64_t max_nodes;          /* per-root intersection budget (0 = none) */
     atomic_uint_fast64_t next;
     /* per-thread results are summed by the caller */
 } job_t;
@@ -294,6 +297,7 @@ typedef struct {
     u128 total;
     uint64_t nodes;
     int status;
+    uint64_t node_limit;         /* abort the current root past this count */
     /* scratch */
     uint32_t *cnt, *touched, *cand;
     uint32_t **S;   /* S[d]: common neighbours at depth d (1..p) */
@@ -313,7 +317,7 @@ static int extend(worker_t *w, uint32_t depth, const uint32_t *S, uint32_t nS,
         uint32_t *S2 = w->S[depth + 1];
         uint32_t n2 = merge_intersect(S, nS, g->adj_u + g->ptr_u[c],
                                       (uint32_t)(g->ptr_u[c + 1] - g->ptr_u[c]), S2);
-        w->nodes++;
+        if (++w->nodes > w->node_limit) return OR_E_BUDGET;
         if (jb->prune && n2 < jb->q) continue;
         if (depth + 1 == jb->p) {
             u128 c_nq = 0;
@@ -390,9 +394,20 @@ static void *worker_main(void *arg)
         if (it >= n_items) break;
         uint64_t r = jb->rank_list ? jb->rank_list[it] : jb->rank_lo + it;
         u128 c = 0;
+        w->node_limit = jb->max_nodes ? w->nodes + jb->max_nodes : UINT64_MAX;
         int rc = count_root(w, jb->by_rank[r], &c);
+        if (rc == OR_E_BUDGET && jb->rank_list) {
+            /* Only per-root queries may give up on a root: it is reported as
+             * not computed and contributes nothing. */
+            jb->per_status[it] = OR_E_BUDGET;
+            continue;
+        }
         if (rc != OR_OK) { w->status = rc; break; }
-        if (jb->rank_list) jb->per_list[it] = c;
+        if (jb->rank_list) {
+            jb->per_list[it] = c;
+            jb->per_status[it] = OR_OK;
+            continue;
+        }
         if (add_u128(&w->total, c) != OR_OK) { w->status = OR_E_OVERFLOW; break; }
     }
     return NULL;
@@ -509,14 +524,17 @@ int oracle_count(uint64_t n_u, uint64_t n_v, const uint64_t *indptr_u, const uin
 /*
  * Per-root counts: for each of the n ranks in rank_list, the number of
  * bicliques whose lowest-ranked L member has that rank, into
- * (out_lo[i], out_hi[i]).
+ * (out_lo[i], out_hi[i]), with out_status[i] = OR_OK.  With max_nodes > 0 a
+ * root that needs more than max_nodes intersections is abandoned and gets
+ * out_status[i] = OR_E_BUDGET (its count is then not computed).
  */
 int oracle_count_ranks(uint64_t n_u, uint64_t n_v, const uint64_t *indptr_u,
                        const uint32_t *indices_u, uint32_t p, uint32_t q, int order_key,
-                       const uint64_t *rank_list, uint64_t n, int threads,
-                       uint64_t *out_lo, uint64_t *out_hi)
+                       const uint64_t *rank_list, uint64_t n, int threads, uint64_t max_nodes,
+                       uint64_t *out_lo, uint64_t *out_hi, int32_t *out_status)
 {
-    if (p == 0 || q == 0 || p > 256 || q > 256 || (n && (!rank_list || !out_lo || !out_hi)))
+    if (p == 0 || q == 0 || p > 256 || q > 256 ||
+        (n && (!rank_list || !out_lo || !out_hi || !out_status)))
         return OR_E_ARG;
     og_graph g;
     int rc = graph_load(&g, n_u, n_v, indptr_u, indices_u);
@@ -543,6 +561,8 @@ int oracle_count_ranks(uint64_t n_u, uint64_t n_v, const uint64_t *indptr_u,
         jb.rank_list = rank_list;
         jb.n_list = n;
         jb.per_list = per;
+        jb.per_status = out_status;
+        jb.max_nodes = max_nodes;
         atomic_init(&jb.next, 0);
         u128 total = 0;
         rc = run_job(&jb, threads, &total, NULL);
@@ -552,6 +572,7 @@ int oracle_count_ranks(uint64_t n_u, uint64_t n_v, const uint64_t *indptr_u,
             out_lo[i] = (uint64_t)per[i];
             out_hi[i] = (uint64_t)(per[i] >> 64);
         }
+
     free(per);
     binom_free(&bt);
     free(rank);

@@ -1,0 +1,238 @@
+"""Python binding of the C ABI in include/bc.h (argument marshalling only).
+
+Every function keeps the C name and runs the device library ``libbc.so``;
+there is no Python or CPU fallback.  Importing this module on a machine
+where the library cannot be loaded raises ImportError.
+
+CSR inputs are host numpy arrays (indptr uint64, indices uint32).  A torch
+stream may be passed as ``stream=torch.cuda.current_stream()`` (or a raw
+``hipStream_t`` integer); the default is the library's own stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbc.so")
+
+BC_OK = 0
+BC_E_INVALID_ARG = -1
+BC_E_BAD_CSR = -2
+BC_E_INCONSISTENT = -3
+BC_E_OOM = -4
+BC_E_DEVICE = -5
+BC_E_OVERFLOW = -6
+BC_E_REJECTED = -7
+BC_E_TIMEOUT = -8
+BC_E_CANCELLED = -9
+BC_E_PENDING = -10
+BC_E_NOT_FOUND = -11
+
+BC_ANCHOR_AUTO, BC_ANCHOR_U, BC_ANCHOR_V = -1, 0, 1
+
+
+class bc_u128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+    @property
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class bc_csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_uint64), ("n_cols", ctypes.c_uint64), ("nnz", ctypes.c_uint64),
+                ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p)]
+
+
+class bc_opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("stream", ctypes.c_void_p), ("anchor", ctypes.c_int32),
+                ("lds_words", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
+                ("instrument", ctypes.c_uint32)]
+
+
+class bc_stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_candidates", ctypes.c_double), ("ms_plan", ctypes.c_double),
+                ("ms_rows", ctypes.c_double), ("ms_enumerate", ctypes.c_double), ("anchor", ctypes.c_int32),
+                ("roots", ctypes.c_uint64), ("roots_active", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
+                ("candidate_edges", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
+                ("pair_ops", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2403_07858_amd/build.py (hipcc, gfx950)")
+    try:
+        lib = ctypes.CDLL(LIB_PATH)
+    except OSError as e:  # pragma: no cover - depends on the machine
+        raise ImportError(f"cannot load {LIB_PATH}: {e}") from e
+    P, I32, U32, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "bc_build": ([P, P, P, P], I32),
+        "bc_free": ([P], None),
+        "bc_graph_info": ([P, P, P, P], I32),
+        "bc_ranks": ([P, I32, P], I32),
+        "bc_count": ([P, U32, U32, P, P, P], I32),
+        "bc_count_roots": ([P, U32, U32, I32, U64, U64, P, P, P], I32),
+        "bc_count_batch": ([P, P, P, SZ, P, P, P], I32),
+        "bc_status_string": ([I32], ctypes.c_char_p),
+        "bc_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_count", "bc_count_roots", "bc_count_batch",
+            "bc_status_string", "bc_last_error")
+
+
+class BCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = bc_last_error()
+        super().__init__(f"{where}: {bc_status_string(status)}" + (f" ({detail})" if detail else ""))
+
+
+def bc_status_string(s: int) -> str:
+    return _lib.bc_status_string(s).decode()
+
+
+def bc_last_error() -> str:
+    return _lib.bc_last_error().decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    h = getattr(stream, "cuda_stream", None)   # torch.cuda.Stream
+    if h is None:
+        raise TypeError("stream must be a torch.cuda.Stream or a raw stream handle")
+    return int(h)
+
+
+def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, instrument=False) -> bc_opts:
+    o = bc_opts()
+    o.struct_size = ctypes.sizeof(bc_opts)
+    o.stream = _stream_handle(stream)
+    o.anchor = anchor
+    o.lds_words = lds_words
+    o.waves_per_cu = waves_per_cu
+    o.instrument = 1 if instrument else 0
+    return o
+
+
+def _csr(n_rows, n_cols, indptr, indices, keep):
+    ip = np.ascontiguousarray(indptr, dtype=np.uint64)
+    ix = np.ascontiguousarray(indices, dtype=np.uint32)
+    keep += [ip, ix]
+    c = bc_csr()
+    c.n_rows, c.n_cols, c.nnz = n_rows, n_cols, int(ix.shape[0])
+    c.indptr = ip.ctypes.data
+    c.indices = ix.ctypes.data if ix.size else None
+    return c
+
+
+class Graph:
+    """A graph resident on the device (owns a ``bc_graph *``)."""
+
+    def __init__(self, handle: int, n_u: int, n_v: int, n_edges: int):
+        self.handle = handle
+        self.n_u, self.n_v, self.n_edges = n_u, n_v, n_edges
+
+    def close(self):
+        if self.handle:
+            _lib.bc_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bc_build(n_u, n_v, indptr_u, indices_u, indptr_v, indices_v, **opt) -> Graph:
+    """Validate and upload a bipartite graph given as its two CSR sides."""
+    keep = []
+    cu = _csr(n_u, n_v, indptr_u, indices_u, keep)
+    cv = _csr(n_v, n_u, indptr_v, indices_v, keep)
+    o = make_opts(**opt)
+    h = ctypes.c_void_p()
+    s = _lib.bc_build(ctypes.byref(cu), ctypes.byref(cv), ctypes.byref(o), ctypes.byref(h))
+    if s != BC_OK:
+        raise BCError(s, "bc_build")
+    return Graph(h.value, n_u, n_v, cu.nnz)
+
+
+def build_graph(g, **opt) -> Graph:
+    """bc_build from any object with n_u, n_v, indptr_u, indices_u, indptr_v, indices_v."""
+    return bc_build(g.n_u, g.n_v, g.indptr_u, g.indices_u, g.indptr_v, g.indices_v, **opt)
+
+
+def bc_free(g: Graph) -> None:
+    g.close()
+
+
+def bc_graph_info(g: Graph):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    s = _lib.bc_graph_info(g.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if s != BC_OK:
+        raise BCError(s, "bc_graph_info")
+    return a.value, b.value, c.value
+
+
+def bc_ranks(g: Graph, side: int) -> np.ndarray:
+    n = g.n_u if side == 0 else g.n_v
+    out = np.zeros(max(1, n), dtype=np.uint32)
+    s = _lib.bc_ranks(g.handle, side, out.ctypes.data)
+    if s != BC_OK:
+        raise BCError(s, "bc_ranks")
+    return out[:n]
+
+
+def bc_count(g: Graph, p: int, q: int, with_stats=False, **opt):
+    """Exact number of (p,q)-bicliques (python int); optionally with stats."""
+    o = make_opts(**opt)
+    out, st = bc_u128(), bc_stats()
+    s = _lib.bc_count(g.handle, p, q, ctypes.byref(o), ctypes.byref(out), ctypes.byref(st))
+    if s != BC_OK:
+        raise BCError(s, "bc_count")
+    return (out.value, st.as_dict()) if with_stats else out.value
+
+
+def bc_count_roots(g: Graph, p: int, q: int, anchor: int, rank_lo: int, rank_hi: int, with_stats=False, **opt):
+    """Partial count over roots with rank in [rank_lo, rank_hi) on the anchor side."""
+    o = make_opts(**opt)
+    out, st = bc_u128(), bc_stats()
+    s = _lib.bc_count_roots(g.handle, p, q, anchor, rank_lo, rank_hi, ctypes.byref(o), ctypes.byref(out),
+                            ctypes.byref(st))
+    if s != BC_OK:
+        raise BCError(s, "bc_count_roots")
+    return (out.value, st.as_dict()) if with_stats else out.value
+
+
+def bc_count_batch(graphs, ps, qs, **opt):
+    """Counts for many (graph, p, q) in one set of launches: (values, statuses)."""
+    n = len(graphs)
+    hs = (ctypes.c_void_p * max(1, n))(*[g.handle for g in graphs])
+    pa = np.ascontiguousarray(ps, dtype=np.uint32)
+    qa = np.ascontiguousarray(qs, dtype=np.uint32)
+    out = (bc_u128 * max(1, n))()
+    st = np.zeros(max(1, n), dtype=np.int32)
+    o = make_opts(**opt)
+    s = _lib.bc_count_batch(hs, pa.ctypes.data, qa.ctypes.data, n, ctypes.byref(o), out, st.ctypes.data)
+    if s != BC_OK:
+        raise BCError(s, "bc_count_batch")
+    return [out[i].value for i in range(n)], [int(x) for x in st[:n]]

@@ -1,0 +1,98 @@
+// Shared declarations between the host library and the HIP kernels of the
+// biclique counter.  Device-side structures hold plain pointers into HBM.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcdev {
+
+typedef unsigned __int128 u128;
+
+// One counting job: (graph side pair, p, q, root range) -> one result slot.
+// "A" is the anchor side (L is drawn from it), "B" the other side.  Both CSRs
+// are relabelled by rank, so orientation "w ranked after u" is "w > u".
+struct Job {
+    const uint64_t *ptrA;   // nA + 1
+    const uint32_t *adjA;   // N(u) as sorted B ids
+    const uint64_t *ptrB;   // nB + 1
+    const uint32_t *adjB;   // N(v) as sorted A ids
+    const u128 *binom;      // binom[n] = C(n, qA) for n in [0, binom_n)
+    uint32_t nA, nB;
+    uint32_t root_lo, root_hi;  // roots counted: ranks in [root_lo, root_hi)
+    uint32_t pA, qA;
+    uint32_t binom_n;       // table length (max degree of A + 1)
+    uint32_t n_ovf;         // smallest n with C(n, qA) >= 2^128 (binom_n if none)
+    uint32_t slot;          // result slot
+    uint32_t pad;
+};
+
+// One root that owns enumeration tasks, in schedule (cost) order.
+struct ActiveRoot {
+    uint64_t pool_off;      // first word of its candidate rows in the pool
+    uint64_t task_begin;    // global index of its first task
+    uint32_t job;
+    uint32_t root;          // anchor-side vertex (rank)
+    uint32_t k;             // number of candidates (rows)
+    uint32_t n_tasks;       // candidates that start a task: k - (pA - 2)
+};
+
+// Result slot: exact 128-bit count as two 64-bit limbs plus status flags.
+struct Slot {
+    unsigned long long lo, hi;
+    unsigned int flags;     // FLAG_* bits
+    unsigned int pad;
+    unsigned long long pair_ops, filter_ops;
+};
+
+enum : unsigned {
+    FLAG_OVERFLOW = 1u,     // count does not fit in 128 bits
+    FLAG_CAPACITY = 2u,     // a scratch bound computed on the host was exceeded
+    FLAG_MISMATCH = 4u,     // candidate count differs between the two wedge passes
+};
+
+constexpr int kWaveSize = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlockThreads = kWaveSize * kWavesPerBlock;
+constexpr int kSortCap = 4096;          // candidates sorted in LDS up to this many
+constexpr uint32_t kSlotFlag = 0x80000000u;
+
+struct RootScratch {
+    uint32_t *cnt;          // per block: nA_max counters, all zero between roots
+    uint32_t *touched;      // per block: nA_max touched ids
+    uint32_t *cand;         // per block: nA_max candidate ids (when k > kSortCap)
+    uint64_t stride;        // elements per block in each array
+};
+
+struct EnumParams {
+    const Job *jobs;
+    const ActiveRoot *roots;
+    uint32_t n_roots;
+    uint64_t n_tasks;
+    const uint64_t *pool;
+    uint64_t *slab;         // per-wave global scratch
+    uint64_t slab_words;    // words per wave
+    uint32_t lds_words;     // per-wave LDS words actually used (<= compiled cap)
+    uint32_t instrument;
+    unsigned long long *queue;   // task counter
+    Slot *slots;
+};
+
+// Launchers (defined in bc_kernels.hip).  All run on `stream` and return the
+// launch status.
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_fill_slots(Slot *slots, uint32_t n, hipStream_t stream);
+hipError_t launch_degree_sum(const Job *jobs, const uint32_t *job_ids, uint32_t n_jobs,
+                             Slot *slots, hipStream_t stream);
+hipError_t launch_cand_count(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
+                             uint64_t total_roots, RootScratch scratch, uint32_t n_blocks,
+                             unsigned long long *queue, uint32_t *out_k, Slot *slots,
+                             hipStream_t stream);
+hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t n_roots,
+                             uint64_t *pool, RootScratch scratch, uint32_t n_blocks,
+                             unsigned long long *queue, Slot *slots, hipStream_t stream);
+hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream);
+
+uint32_t max_lds_words_per_wave();
+
+}  // namespace bcdev

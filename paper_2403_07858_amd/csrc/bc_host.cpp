@@ -1,0 +1,791 @@
+// Host side of the biclique counter: input validation, degree-order
+// relabelling, device residency of graphs, per-query planning and the C ABI
+// declared in include/bc.h.
+#include "bc.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bc_device.h"
+
+using bcdev::u128;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bc_status set_error(bc_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+bc_status hip_error(hipError_t e, const char *what)
+{
+    return set_error(BC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BC_HIP(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_error(e_, #call);       \
+    } while (0)
+
+unsigned host_threads()
+{
+    unsigned n = std::thread::hardware_concurrency();
+    return n ? std::min(n, 16u) : 1u;
+}
+
+template <typename F>
+void parallel_for(uint64_t n, F f)
+{
+    unsigned t = host_threads();
+    if (n < 65536 || t <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    uint64_t chunk = (n + t - 1) / t;
+    for (unsigned i = 0; i < t; ++i) {
+        uint64_t b = i * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back([=] { f(b, e); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
+// Graph residency.
+
+struct Side {
+    uint64_t n = 0;
+    uint32_t max_deg = 0;
+    std::vector<uint32_t> rank_of;   // original id -> rank
+    std::vector<uint64_t> h_ptr;     // relabelled CSR on the host (by rank)
+    uint64_t *d_ptr = nullptr;
+    uint32_t *d_adj = nullptr;
+};
+
+}  // namespace
+
+struct bc_graph {
+    Side side[2];
+    uint64_t nnz = 0;
+    int device = 0;
+};
+
+namespace {
+
+hipStream_t own_stream()
+{
+    thread_local hipStream_t s = nullptr;
+    if (!s) {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    }
+    return s;
+}
+
+hipStream_t pick_stream(const bc_opts *o)
+{
+    if (o && o->stream) return (hipStream_t)o->stream;
+    return own_stream();
+}
+
+bc_status check_opts(const bc_opts *o)
+{
+    if (!o) return BC_OK;
+    if (o->struct_size != 0 && o->struct_size < sizeof(uint32_t) * 2)
+        return set_error(BC_E_INVALID_ARG, "bc_opts.struct_size too small");
+    if (o->anchor < -1 || o->anchor > 1) return set_error(BC_E_INVALID_ARG, "bc_opts.anchor must be -1, 0 or 1");
+    return BC_OK;
+}
+
+// Validates one CSR side; writes sorted rows into rows_out (same layout).
+bc_status validate_side(const bc_csr *c, const char *name, std::vector<uint32_t> &rows_out)
+{
+    if (!c->indptr) return set_error(BC_E_INVALID_ARG, std::string(name) + ".indptr is NULL");
+    if (c->nnz && !c->indices) return set_error(BC_E_INVALID_ARG, std::string(name) + ".indices is NULL");
+    if (c->n_rows >= 0xffffffffull || c->n_cols >= 0xffffffffull)
+        return set_error(BC_E_INVALID_ARG, std::string(name) + ": more than 2^32-2 vertices on a side");
+    if (c->indptr[0] != 0) return set_error(BC_E_BAD_CSR, std::string(name) + ".indptr[0] != 0");
+    for (uint64_t r = 0; r < c->n_rows; ++r)
+        if (c->indptr[r + 1] < c->indptr[r])
+            return set_error(BC_E_BAD_CSR, std::string(name) + ".indptr decreases at row " + std::to_string(r));
+    if (c->indptr[c->n_rows] != c->nnz)
+        return set_error(BC_E_BAD_CSR, std::string(name) + ".indptr[n_rows] != nnz");
+    rows_out.assign(c->indices, c->indices + c->nnz);
+    std::vector<std::string> errs(host_threads() + 1);
+    std::mutex mu;
+    std::string first_err;
+    parallel_for(c->n_rows, [&](uint64_t b, uint64_t e) {
+        for (uint64_t r = b; r < e; ++r) {
+            uint32_t *lo = rows_out.data() + c->indptr[r], *hi = rows_out.data() + c->indptr[r + 1];
+            std::sort(lo, hi);
+            for (uint32_t *x = lo; x < hi; ++x) {
+                if (*x >= c->n_cols || (x > lo && *x == x[-1])) {
+                    std::lock_guard<std::mutex> g(mu);
+                    if (first_err.empty())
+                        first_err = std::string(name) + ": row " + std::to_string(r) +
+                                    (*x >= c->n_cols ? " has an id out of range" : " has a duplicate id");
+                    return;
+                }
+            }
+        }
+    });
+    if (!first_err.empty()) return set_error(BC_E_BAD_CSR, first_err);
+    return BC_OK;
+}
+
+// Rank order of one side: ascending degree, ties by original id.
+void degree_order(const bc_csr *c, std::vector<uint32_t> &id_of_rank, std::vector<uint32_t> &rank_of)
+{
+    const uint64_t n = c->n_rows;
+    id_of_rank.resize(n);
+    std::iota(id_of_rank.begin(), id_of_rank.end(), 0u);
+    std::stable_sort(id_of_rank.begin(), id_of_rank.end(), [&](uint32_t a, uint32_t b) {
+        return (c->indptr[a + 1] - c->indptr[a]) < (c->indptr[b + 1] - c->indptr[b]);
+    });
+    rank_of.resize(n);
+    for (uint64_t r = 0; r < n; ++r) rank_of[id_of_rank[r]] = (uint32_t)r;
+}
+
+// Relabelled CSR: row r is vertex id_of_rank[r]; neighbours mapped through
+// the other side's rank and sorted.
+void relabel(const bc_csr *c, const std::vector<uint32_t> &sorted_rows, const std::vector<uint32_t> &id_of_rank,
+             const std::vector<uint32_t> &other_rank_of, std::vector<uint64_t> &ptr, std::vector<uint32_t> &adj)
+{
+    const uint64_t n = c->n_rows;
+    ptr.assign(n + 1, 0);
+    for (uint64_t r = 0; r < n; ++r) {
+        uint32_t x = id_of_rank[r];
+        ptr[r + 1] = ptr[r] + (c->indptr[x + 1] - c->indptr[x]);
+    }
+    adj.resize(c->nnz);
+    parallel_for(n, [&](uint64_t b, uint64_t e) {
+        for (uint64_t r = b; r < e; ++r) {
+            uint32_t x = id_of_rank[r];
+            uint64_t s = c->indptr[x], t = c->indptr[x + 1], o = ptr[r];
+            for (uint64_t i = s; i < t; ++i) adj[o + (i - s)] = other_rank_of[sorted_rows[i]];
+            std::sort(adj.begin() + o, adj.begin() + o + (t - s));
+        }
+    });
+}
+
+void free_side(Side &s)
+{
+    if (s.d_ptr) (void)hipFree(s.d_ptr);
+    if (s.d_adj) (void)hipFree(s.d_adj);
+    s.d_ptr = nullptr;
+    s.d_adj = nullptr;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *opts, bc_graph **out)
+{
+    g_last_error.clear();
+    if (!U || !V || !out) return set_error(BC_E_INVALID_ARG, "bc_build: NULL argument");
+    if (bc_status s = check_opts(opts)) return s;
+    if (U->n_rows != V->n_cols || U->n_cols != V->n_rows)
+        return set_error(BC_E_INCONSISTENT, "bc_build: U and V CSR shapes are not transposes");
+    if (U->nnz != V->nnz) return set_error(BC_E_INCONSISTENT, "bc_build: U and V have different edge counts");
+    std::vector<uint32_t> rowsU, rowsV;
+    if (bc_status s = validate_side(U, "U", rowsU)) return s;
+    if (bc_status s = validate_side(V, "V", rowsV)) return s;
+
+    // V must be the transpose of U: build the transpose of U (rows come out
+    // sorted because u is visited in increasing order) and compare.
+    {
+        std::vector<uint64_t> tp(V->n_rows + 1, 0);
+        for (uint64_t i = 0; i < U->nnz; ++i) tp[rowsU[i] + 1]++;
+        for (uint64_t v = 0; v < V->n_rows; ++v) tp[v + 1] += tp[v];
+        for (uint64_t v = 0; v <= V->n_rows; ++v)
+            if (tp[v] != V->indptr[v])
+                return set_error(BC_E_INCONSISTENT, "bc_build: degree of V vertex " +
+                                                        std::to_string(v ? v - 1 : 0) + " differs from U's view");
+        std::vector<uint64_t> fill(tp.begin(), tp.end() - 1);
+        std::vector<uint32_t> tadj(U->nnz);
+        for (uint64_t u = 0; u < U->n_rows; ++u)
+            for (uint64_t i = U->indptr[u]; i < U->indptr[u + 1]; ++i) tadj[fill[rowsU[i]]++] = (uint32_t)u;
+        if (tadj != rowsV) return set_error(BC_E_INCONSISTENT, "bc_build: V is not the transpose of U");
+    }
+
+    bc_graph *g = new (std::nothrow) bc_graph();
+    if (!g) return set_error(BC_E_OOM, "bc_build: host allocation failed");
+    g->nnz = U->nnz;
+    (void)hipGetDevice(&g->device);
+    std::vector<uint32_t> idU, idV;
+    degree_order(U, idU, g->side[0].rank_of);
+    degree_order(V, idV, g->side[1].rank_of);
+    const bc_csr *cs[2] = {U, V};
+    const std::vector<uint32_t> *rows[2] = {&rowsU, &rowsV};
+    const std::vector<uint32_t> *ids[2] = {&idU, &idV};
+    hipStream_t st = pick_stream(opts);
+    for (int s = 0; s < 2; ++s) {
+        Side &sd = g->side[s];
+        sd.n = cs[s]->n_rows;
+        std::vector<uint32_t> adj;
+        relabel(cs[s], *rows[s], *ids[s], g->side[1 - s].rank_of, sd.h_ptr, adj);
+        for (uint64_t r = 0; r < sd.n; ++r)
+            sd.max_deg = std::max<uint32_t>(sd.max_deg, (uint32_t)(sd.h_ptr[r + 1] - sd.h_ptr[r]));
+        hipError_t e = hipMalloc(&sd.d_ptr, (sd.n + 1) * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc(&sd.d_adj, std::max<uint64_t>(1, g->nnz) * sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sd.d_ptr, sd.h_ptr.data(), (sd.n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && g->nnz)
+            e = hipMemcpyAsync(sd.d_adj, adj.data(), g->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_side(g->side[0]);
+            free_side(g->side[1]);
+            delete g;
+            return e == hipErrorOutOfMemory ? set_error(BC_E_OOM, "bc_build: device allocation failed")
+                                            : hip_error(e, "bc_build: upload");
+        }
+    }
+    *out = g;
+    return BC_OK;
+}
+
+extern "C" void bc_free(bc_graph *g)
+{
+    if (!g) return;
+    free_side(g->side[0]);
+    free_side(g->side[1]);
+    delete g;
+}
+
+extern "C" bc_status bc_graph_info(const bc_graph *g, uint64_t *n_u, uint64_t *n_v, uint64_t *n_edges)
+{
+    if (!g) return set_error(BC_E_INVALID_ARG, "bc_graph_info: NULL graph");
+    if (n_u) *n_u = g->side[0].n;
+    if (n_v) *n_v = g->side[1].n;
+    if (n_edges) *n_edges = g->nnz;
+    return BC_OK;
+}
+
+extern "C" bc_status bc_ranks(const bc_graph *g, int32_t side, uint32_t *rank_of)
+{
+    if (!g || !rank_of || (side != 0 && side != 1)) return set_error(BC_E_INVALID_ARG, "bc_ranks: bad argument");
+    const auto &r = g->side[side].rank_of;
+    std::copy(r.begin(), r.end(), rank_of);
+    return BC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Query execution.
+
+namespace {
+
+struct JobSpec {
+    const bc_graph *g;
+    uint32_t p, q;
+    int32_t anchor;            // requested (AUTO allowed)
+    uint64_t rank_lo, rank_hi; // only used when ranged
+    bool ranged;
+};
+
+// C(n, q) for n in [0, nmax] as exact u128; n_ovf = first n that overflows.
+void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n_ovf)
+{
+    std::vector<u128> c(q + 1, 0);
+    std::vector<uint8_t> ov(q + 1, 0);
+    c[0] = 1;
+    col.assign(nmax + 1, 0);
+    n_ovf = nmax + 1;
+    for (uint32_t n = 0; n <= nmax; ++n) {
+        if (n > 0) {
+            for (uint32_t k = std::min(n, q); k >= 1; --k) {
+                u128 s = c[k] + c[k - 1];
+                bool o = ov[k] || ov[k - 1] || s < c[k];
+                c[k] = o ? 0 : s;
+                ov[k] = o;
+            }
+        }
+        if (ov[q] && n_ovf > nmax) n_ovf = n;
+        col[n] = ov[q] ? 0 : c[q];
+    }
+}
+
+struct DevAlloc {
+    std::vector<void *> ptrs;
+    hipStream_t st;
+    explicit DevAlloc(hipStream_t s) : st(s) {}
+    ~DevAlloc()
+    {
+        for (void *p : ptrs) (void)hipFreeAsync(p, st);
+    }
+    template <typename T>
+    hipError_t get(T **p, uint64_t count)
+    {
+        void *v = nullptr;
+        hipError_t e = hipMallocAsync(&v, std::max<uint64_t>(count, 1) * sizeof(T), st);
+        if (e == hipSuccess) ptrs.push_back(v);
+        *p = (T *)v;
+        return e;
+    }
+};
+
+hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) { return bcdev::launch_fill_u32(p, n, v, st); }
+
+int cu_count(int device)
+{
+    static std::mutex mu;
+    static std::vector<int> cache(64, 0);
+    std::lock_guard<std::mutex> g(mu);
+    if (device < 0 || device >= 64) return 256;
+    if (!cache[device]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0) v = 256;
+        cache[device] = v;
+    }
+    return cache[device];
+}
+
+struct Timer {
+    hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ok = true;
+    Timer()
+    {
+        for (auto &x : e)
+            if (hipEventCreate(&x) != hipSuccess) ok = false;
+    }
+    ~Timer()
+    {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    void mark(int i, hipStream_t s)
+    {
+        if (ok) (void)hipEventRecord(e[i], s);
+    }
+    double ms(int a, int b)
+    {
+        float f = 0;
+        if (!ok || hipEventElapsedTime(&f, e[a], e[b]) != hipSuccess) return 0.0;
+        return f;
+    }
+};
+
+// Resolved per-job state on the host.
+struct HostJob {
+    int spec;                  // index into specs
+    int anchor;
+    uint32_t pA, qA;
+    uint32_t root_lo, root_hi;
+    bool trivial_zero;
+    uint64_t cost;             // planning proxy after the candidate pass
+};
+
+bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::vector<bc_u128> &out,
+                   std::vector<bc_status> &item_status, bc_stats *stats)
+{
+    const size_t ns = specs.size();
+    out.assign(ns, bc_u128{0, 0});
+    item_status.assign(ns, BC_OK);
+    if (ns == 0) return BC_OK;
+    hipStream_t st = pick_stream(opts);
+    if (!st) return set_error(BC_E_DEVICE, "could not create a HIP stream");
+    const int device = specs[0].g->device;
+    BC_HIP(hipSetDevice(device));
+    const uint32_t lds_words = (opts && opts->lds_words) ? opts->lds_words : bcdev::max_lds_words_per_wave();
+    const uint32_t waves_per_cu = (opts && opts->waves_per_cu) ? std::max(4u, opts->waves_per_cu) : 8u;
+    const bool instrument = opts && opts->instrument;
+    const int ncu = cu_count(device);
+    auto t_host0 = std::chrono::steady_clock::now();
+
+    // 1. Resolve anchors.  A spec with AUTO and p == q (>= 3) gets both sides
+    //    as candidate jobs; the cheaper by the candidate-pass proxy is kept.
+    std::vector<HostJob> jobs;
+    std::vector<std::vector<int>> spec_jobs(ns);
+    for (size_t i = 0; i < ns; ++i) {
+        const JobSpec &sp = specs[i];
+        std::vector<int> sides;
+        if (sp.anchor == BC_ANCHOR_U || sp.anchor == BC_ANCHOR_V) sides.push_back(sp.anchor);
+        else if (sp.p < sp.q) sides.push_back(0);
+        else if (sp.q < sp.p) sides.push_back(1);
+        else if (sp.p <= 2) sides.push_back(0);
+        else {
+            sides.push_back(0);
+            sides.push_back(1);
+        }
+        for (int a : sides) {
+            HostJob hj{};
+            hj.spec = (int)i;
+            hj.anchor = a;
+            hj.pA = a == 0 ? sp.p : sp.q;
+            hj.qA = a == 0 ? sp.q : sp.p;
+            const Side &A = sp.g->side[a];
+            const Side &B = sp.g->side[1 - a];
+            uint64_t lo = sp.ranged ? std::min<uint64_t>(sp.rank_lo, A.n) : 0;
+            uint64_t hi = sp.ranged ? std::min<uint64_t>(sp.rank_hi, A.n) : A.n;
+            if (hi < lo) hi = lo;
+            hj.root_lo = (uint32_t)lo;
+            hj.root_hi = (uint32_t)hi;
+            hj.trivial_zero = hj.pA > A.n || hj.qA > B.n || lo == hi || hj.qA > A.max_deg;
+            spec_jobs[i].push_back((int)jobs.size());
+            jobs.push_back(hj);
+        }
+    }
+    const uint32_t nj = (uint32_t)jobs.size();
+
+    // 2. Device job table and binomial columns.
+    std::vector<bcdev::Job> hjobs(nj);
+    std::vector<uint64_t> tab_off(nj + 1, 0);
+    std::vector<std::vector<u128>> cols(nj);
+    for (uint32_t j = 0; j < nj; ++j) {
+        const HostJob &hj = jobs[j];
+        const bc_graph *g = specs[hj.spec].g;
+        const Side &A = g->side[hj.anchor];
+        uint32_t n_ovf = 0;
+        binom_column(A.max_deg, hj.qA, cols[j], n_ovf);
+        bcdev::Job &d = hjobs[j];
+        memset(&d, 0, sizeof(d));
+        d.ptrA = A.d_ptr;
+        d.adjA = A.d_adj;
+        d.ptrB = g->side[1 - hj.anchor].d_ptr;
+        d.adjB = g->side[1 - hj.anchor].d_adj;
+        d.nA = (uint32_t)A.n;
+        d.nB = (uint32_t)g->side[1 - hj.anchor].n;
+        d.root_lo = hj.root_lo;
+        d.root_hi = hj.root_hi;
+        d.pA = hj.pA;
+        d.qA = hj.qA;
+        d.binom_n = A.max_deg + 1;
+        d.n_ovf = n_ovf;
+        d.slot = j;
+        tab_off[j + 1] = tab_off[j] + cols[j].size();
+    }
+    DevAlloc mem(st);
+    bcdev::Job *d_jobs;
+    u128 *d_tab;
+    bcdev::Slot *d_slots;
+    unsigned long long *d_queue;
+    BC_HIP(mem.get(&d_jobs, nj));
+    BC_HIP(mem.get(&d_tab, tab_off[nj]));
+    BC_HIP(mem.get(&d_slots, nj));
+    BC_HIP(mem.get(&d_queue, 4));
+    {
+        std::vector<u128> tab(tab_off[nj]);
+        for (uint32_t j = 0; j < nj; ++j) {
+            std::copy(cols[j].begin(), cols[j].end(), tab.begin() + tab_off[j]);
+            hjobs[j].binom = d_tab + tab_off[j];
+        }
+        BC_HIP(hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(u128), hipMemcpyHostToDevice, st));
+        BC_HIP(hipMemcpyAsync(d_jobs, hjobs.data(), nj * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
+        BC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+    }
+    BC_HIP(bcdev::launch_fill_slots(d_slots, nj, st));
+    BC_HIP(fill_u32((uint32_t *)d_queue, 8, 0u, st));
+
+    Timer tm;
+    tm.mark(0, st);
+
+    // 3. pA == 1: degree sums.
+    std::vector<uint32_t> deg_jobs;
+    for (uint32_t j = 0; j < nj; ++j)
+        if (!jobs[j].trivial_zero && jobs[j].pA == 1) deg_jobs.push_back(j);
+    if (!deg_jobs.empty()) {
+        uint32_t *d_ids;
+        BC_HIP(mem.get(&d_ids, deg_jobs.size()));
+        BC_HIP(hipMemcpyAsync(d_ids, deg_jobs.data(), deg_jobs.size() * 4, hipMemcpyHostToDevice, st));
+        BC_HIP(bcdev::launch_degree_sum(d_jobs, d_ids, (uint32_t)deg_jobs.size(), d_slots, st));
+    }
+
+    // 4. Candidate pass over all roots of jobs with pA >= 2.
+    std::vector<uint32_t> cj;   // jobs in the candidate pass
+    std::vector<uint64_t> root_prefix(1, 0);
+    uint32_t nA_max = 1;
+    for (uint32_t j = 0; j < nj; ++j) {
+        if (jobs[j].trivial_zero || jobs[j].pA < 2) continue;
+        cj.push_back(j);
+        root_prefix.push_back(root_prefix.back() + (jobs[j].root_hi - jobs[j].root_lo));
+        nA_max = std::max(nA_max, hjobs[j].nA);
+    }
+    const uint64_t total_roots = root_prefix.back();
+    std::vector<uint32_t> h_k(total_roots);
+    bcdev::RootScratch rs{};
+    const uint32_t root_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(total_roots, 1), (uint64_t)ncu * 2);
+    std::vector<bcdev::Job> cjobs;
+    bcdev::Job *d_cjobs = nullptr;
+    if (total_roots) {
+        // the candidate pass runs over its own compact job table
+        cjobs.reserve(cj.size());
+        for (uint32_t j : cj) cjobs.push_back(hjobs[j]);
+        uint64_t *d_rp;
+        uint32_t *d_k;
+        BC_HIP(mem.get(&d_cjobs, cjobs.size()));
+        BC_HIP(mem.get(&d_rp, root_prefix.size()));
+        BC_HIP(mem.get(&d_k, total_roots));
+        rs.stride = nA_max;
+        BC_HIP(mem.get(&rs.cnt, (uint64_t)root_blocks * nA_max));
+        BC_HIP(mem.get(&rs.touched, (uint64_t)root_blocks * nA_max));
+        BC_HIP(mem.get(&rs.cand, (uint64_t)root_blocks * nA_max));
+        BC_HIP(fill_u32(rs.cnt, (uint64_t)root_blocks * nA_max, 0u, st));
+        BC_HIP(hipMemcpyAsync(d_cjobs, cjobs.data(), cjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
+        BC_HIP(hipMemcpyAsync(d_rp, root_prefix.data(), root_prefix.size() * 8, hipMemcpyHostToDevice, st));
+        BC_HIP(bcdev::launch_cand_count(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, root_blocks, d_queue + 0,
+                                        d_k, d_slots, st));
+        BC_HIP(hipMemcpyAsync(h_k.data(), d_k, total_roots * 4, hipMemcpyDeviceToHost, st));
+    }
+    tm.mark(1, st);
+    BC_HIP(hipStreamSynchronize(st));
+    auto t_plan0 = std::chrono::steady_clock::now();
+
+    // 5. Plan: per-job cost proxies, anchor choice, active roots, pool.
+    std::vector<char> job_live(nj, 1);
+    for (uint32_t c = 0; c < cj.size(); ++c) {
+        const uint32_t j = cj[c];
+        const HostJob &hj = jobs[j];
+        const Side &A = specs[hj.spec].g->side[hj.anchor];
+        uint64_t cost = 0;
+        const uint32_t e = std::min<uint32_t>(hj.pA - 1, 3);
+        for (uint64_t r = root_prefix[c]; r < root_prefix[c + 1]; ++r) {
+            uint64_t k = h_k[r];
+            uint64_t u = hj.root_lo + (r - root_prefix[c]);
+            uint64_t w1 = (A.h_ptr[u + 1] - A.h_ptr[u] + 63) / 64;
+            uint64_t x = k * w1;
+            for (uint32_t t = 1; t < e; ++t) x = std::min<uint64_t>(x * k, 1ull << 62);
+            cost = std::min<uint64_t>(cost + x, 1ull << 62);
+        }
+        jobs[j].cost = cost;
+    }
+    for (size_t i = 0; i < ns; ++i) {
+        if (spec_jobs[i].size() == 2) {
+            int a = spec_jobs[i][0], b = spec_jobs[i][1];
+            if (jobs[b].cost < jobs[a].cost) std::swap(a, b);
+            job_live[b] = 0;
+            spec_jobs[i] = {a};
+        }
+    }
+    struct Plan {
+        uint32_t c;  // index into cj / cjobs
+        uint32_t root, k, w1;
+        uint64_t cost;
+    };
+    std::vector<Plan> plan;
+    uint64_t cand_edges = 0;
+    for (uint32_t c = 0; c < cj.size(); ++c) {
+        const uint32_t j = cj[c];
+        if (!job_live[j]) continue;
+        const HostJob &hj = jobs[j];
+        const Side &A = specs[hj.spec].g->side[hj.anchor];
+        for (uint64_t r = root_prefix[c]; r < root_prefix[c + 1]; ++r) {
+            cand_edges += h_k[r];
+            if (hj.pA < 3 || h_k[r] < hj.pA - 1) continue;
+            uint32_t u = (uint32_t)(hj.root_lo + (r - root_prefix[c]));
+            uint32_t w1 = (uint32_t)((A.h_ptr[u + 1] - A.h_ptr[u] + 63) / 64);
+            uint64_t k = h_k[r];
+            uint64_t x = k * w1;
+            const uint32_t e = std::min<uint32_t>(hj.pA - 1, 3);
+            for (uint32_t t = 1; t < e; ++t) x = std::min<uint64_t>(x * k, 1ull << 62);
+            plan.push_back(Plan{c, u, (uint32_t)k, w1, x});
+        }
+    }
+    std::stable_sort(plan.begin(), plan.end(), [](const Plan &a, const Plan &b) { return a.cost > b.cost; });
+    std::vector<bcdev::ActiveRoot> aroots(plan.size());
+    uint64_t pool_words = 0, tasks = 0, slab_need = 64;
+    for (size_t r = 0; r < plan.size(); ++r) {
+        const Plan &pl = plan[r];
+        const uint32_t pA = cjobs[pl.c].pA;
+        bcdev::ActiveRoot &a = aroots[r];
+        a.pool_off = pool_words;
+        a.task_begin = tasks;
+        a.job = pl.c;
+        a.root = pl.root;
+        a.k = pl.k;
+        a.n_tasks = pl.k - (pA - 2);
+        pool_words += (uint64_t)pl.k * pl.w1;
+        tasks += a.n_tasks;
+        uint64_t need = 2ull * pl.w1 + (pA >= 4 ? (uint64_t)(pA - 3) * (pl.k - 1) * pl.w1 : 0) + 8;
+        slab_need = std::max(slab_need, need);
+    }
+    const double ms_plan =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan0).count();
+
+    tm.mark(2, st);
+    if (!plan.empty()) {
+        bcdev::ActiveRoot *d_roots;
+        uint64_t *d_pool;
+        BC_HIP(mem.get(&d_roots, aroots.size()));
+        BC_HIP(mem.get(&d_pool, pool_words));
+        BC_HIP(hipMemcpyAsync(d_roots, aroots.data(), aroots.size() * sizeof(bcdev::ActiveRoot), hipMemcpyHostToDevice,
+                              st));
+        BC_HIP(bcdev::launch_rows_build(d_cjobs, d_roots, (uint32_t)aroots.size(), d_pool, rs, root_blocks, d_queue + 1,
+                                        d_slots, st));
+        tm.mark(3, st);
+        // Enumeration grid: waves_per_cu wavefronts per CU; each wave owns a
+        // slab big enough for the deepest task of this plan.
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ncu * waves_per_cu / bcdev::kWavesPerBlock);
+        const uint64_t slab_budget = 64ull << 30;   // bytes of HBM for all slabs
+        while (blocks > 1 && (uint64_t)blocks * bcdev::kWavesPerBlock * slab_need * 8 > slab_budget) blocks /= 2;
+        uint64_t *d_slab;
+        BC_HIP(mem.get(&d_slab, (uint64_t)blocks * bcdev::kWavesPerBlock * slab_need));
+        bcdev::EnumParams prm{};
+        prm.jobs = d_cjobs;
+        prm.roots = d_roots;
+        prm.n_roots = (uint32_t)aroots.size();
+        prm.n_tasks = tasks;
+        prm.pool = d_pool;
+        prm.slab = d_slab;
+        prm.slab_words = slab_need;
+        prm.lds_words = lds_words;
+        prm.instrument = instrument ? 1u : 0u;
+        prm.queue = d_queue + 2;
+        prm.slots = d_slots;
+        BC_HIP(bcdev::launch_enumerate(prm, blocks, st));
+    } else {
+        tm.mark(3, st);
+    }
+    tm.mark(4, st);
+    std::vector<bcdev::Slot> hs(nj);
+    BC_HIP(hipMemcpyAsync(hs.data(), d_slots, nj * sizeof(bcdev::Slot), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+
+    // 6. Results.  Candidate jobs for the same spec: only the live one counts.
+    bc_status overall = BC_OK;
+    for (size_t i = 0; i < ns; ++i) {
+        const int j = spec_jobs[i][0];
+        const bcdev::Slot &s = hs[j];
+        if (jobs[j].trivial_zero) {
+            out[i] = bc_u128{0, 0};
+            continue;
+        }
+        if (s.flags & bcdev::FLAG_OVERFLOW) {
+            item_status[i] = BC_E_OVERFLOW;
+            g_last_error = "count exceeds 128 bits";
+        } else if (s.flags & (bcdev::FLAG_CAPACITY | bcdev::FLAG_MISMATCH)) {
+            item_status[i] = BC_E_DEVICE;
+            g_last_error = (s.flags & bcdev::FLAG_CAPACITY) ? "internal: enumeration scratch bound exceeded"
+                                                             : "internal: candidate passes disagree";
+            overall = BC_E_DEVICE;
+        } else {
+            out[i] = bc_u128{s.lo, s.hi};
+        }
+    }
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->ms_candidates = tm.ms(0, 1);
+        stats->ms_plan = ms_plan;
+        stats->ms_rows = tm.ms(2, 3);
+        stats->ms_enumerate = tm.ms(3, 4);
+        stats->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
+        stats->anchor = jobs[spec_jobs[0][0]].anchor;
+        stats->roots = total_roots;
+        stats->roots_active = plan.size();
+        stats->tasks = tasks;
+        stats->candidate_edges = cand_edges;
+        stats->row_words = pool_words;
+        for (size_t i = 0; i < ns; ++i) {
+            stats->pair_ops += hs[spec_jobs[i][0]].pair_ops;
+            stats->filter_ops += hs[spec_jobs[i][0]].filter_ops;
+        }
+    }
+    return overall;
+}
+
+bc_status check_pq(uint32_t p, uint32_t q)
+{
+    if (p < 1 || q < 1 || p > 32 || q > 32) return set_error(BC_E_INVALID_ARG, "p and q must be in 1..32");
+    return BC_OK;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_count(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts, bc_u128 *out,
+                              bc_stats *st)
+{
+    g_last_error.clear();
+    if (!g || !out) return set_error(BC_E_INVALID_ARG, "bc_count: NULL argument");
+    if (bc_status s = check_pq(p, q)) return s;
+    if (bc_status s = check_opts(opts)) return s;
+    std::vector<JobSpec> sp{JobSpec{g, p, q, opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false}};
+    std::vector<bc_u128> res;
+    std::vector<bc_status> ist;
+    bc_status s = run_jobs(sp, opts, res, ist, st);
+    if (s != BC_OK) return s;
+    if (ist[0] != BC_OK) return ist[0];
+    *out = res[0];
+    return BC_OK;
+}
+
+extern "C" bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor, uint64_t rank_lo,
+                                    uint64_t rank_hi, const bc_opts *opts, bc_u128 *out, bc_stats *st)
+{
+    g_last_error.clear();
+    if (!g || !out) return set_error(BC_E_INVALID_ARG, "bc_count_roots: NULL argument");
+    if (bc_status s = check_pq(p, q)) return s;
+    if (bc_status s = check_opts(opts)) return s;
+    if (anchor != BC_ANCHOR_U && anchor != BC_ANCHOR_V)
+        return set_error(BC_E_INVALID_ARG, "bc_count_roots: anchor must be BC_ANCHOR_U or BC_ANCHOR_V");
+    if (rank_lo > rank_hi) return set_error(BC_E_INVALID_ARG, "bc_count_roots: rank_lo > rank_hi");
+    std::vector<JobSpec> sp{JobSpec{g, p, q, anchor, rank_lo, rank_hi, true}};
+    std::vector<bc_u128> res;
+    std::vector<bc_status> ist;
+    bc_status s = run_jobs(sp, opts, res, ist, st);
+    if (s != BC_OK) return s;
+    if (ist[0] != BC_OK) return ist[0];
+    *out = res[0];
+    return BC_OK;
+}
+
+extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
+                                    const bc_opts *opts, bc_u128 *out, bc_status *item_status)
+{
+    g_last_error.clear();
+    if (n == 0) return BC_OK;
+    if (!graphs || !p || !q || !out || !item_status) return set_error(BC_E_INVALID_ARG, "bc_count_batch: NULL argument");
+    if (bc_status s = check_opts(opts)) return s;
+    std::vector<JobSpec> sp;
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < n; ++i) {
+        if (!graphs[i] || p[i] < 1 || q[i] < 1 || p[i] > 32 || q[i] > 32) {
+            item_status[i] = BC_E_INVALID_ARG;
+            continue;
+        }
+        if (graphs[i]->device != graphs[0]->device)
+            return set_error(BC_E_INVALID_ARG, "bc_count_batch: graphs on different devices");
+        item_status[i] = BC_OK;
+        idx.push_back(i);
+        sp.push_back(JobSpec{graphs[i], p[i], q[i], opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false});
+    }
+    std::vector<bc_u128> res;
+    std::vector<bc_status> ist;
+    bc_status s = run_jobs(sp, opts, res, ist, nullptr);
+    if (s != BC_OK && s != BC_E_DEVICE) return s;
+    for (size_t t = 0; t < idx.size(); ++t) {
+        item_status[idx[t]] = ist[t];
+        out[idx[t]] = ist[t] == BC_OK ? res[t] : bc_u128{0, 0};
+    }
+    return s;
+}
+
+extern "C" const char *bc_status_string(bc_status s)
+{
+    switch (s) {
+    case BC_OK: return "BC_OK";
+    case BC_E_INVALID_ARG: return "BC_E_INVALID_ARG";
+    case BC_E_BAD_CSR: return "BC_E_BAD_CSR";
+    case BC_E_INCONSISTENT: return "BC_E_INCONSISTENT";
+    case BC_E_OOM: return "BC_E_OOM";
+    case BC_E_DEVICE: return "BC_E_DEVICE";
+    case BC_E_OVERFLOW: return "BC_E_OVERFLOW";
+    case BC_E_REJECTED: return "BC_E_REJECTED";
+    case BC_E_TIMEOUT: return "BC_E_TIMEOUT";
+    case BC_E_CANCELLED: return "BC_E_CANCELLED";
+    case BC_E_PENDING: return "BC_E_PENDING";
+    case BC_E_NOT_FOUND: return "BC_E_NOT_FOUND";
+    default: return "BC_E_UNKNOWN";
+    }
+}
+
+extern "C" const char *bc_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,756 @@
+// HIP kernels of the (p,q)-biclique counter for CDNA4 (gfx950, wave64).
+//
+// The search follows Algorithm 1 (GBC) restated for this hardware:
+//   k_cand_count  per root u: oriented 2-hop candidates w > u sharing at least
+//                 qA neighbours with u (N_2^q(u) of Section II-A with the
+//                 vertex-priority orientation of Section III-B).  For pA == 2
+//                 the leaves C(|N(u) n N(w)|, qA) are summed right here.
+//   k_rows_build  per root u: one bitmap row per candidate w over the local
+//                 ids of N(u) (bit j set when the j-th neighbour of u is also
+//                 a neighbour of w) -- a truncated bitmap in the spirit of the
+//                 HTB of Section V-A, dense over the root's own neighbourhood.
+//   k_enumerate   persistent wavefronts pop (root, second vertex) tasks -- the
+//                 edge-oriented pre-runtime split of Section V-C -- from one
+//                 device queue (runtime balancing, Section V-C), compact the
+//                 rows to the common neighbours of the two vertices, then run
+//                 the hybrid DFS-BFS of Section IV: DFS over levels, all
+//                 siblings of a node intersected at once by the 64 lanes
+//                 (AND + popcount), and the last two levels fused into one
+//                 pairwise sum of C(|S|, q) (leaf rule of Section III-A).
+#include "bc_device.h"
+
+namespace bcdev {
+
+constexpr uint32_t kLdsWordsPerWave = 2048;   // 16 KiB of LDS per wavefront
+constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
+
+
+uint32_t max_lds_words_per_wave() { return kLdsWordsPerWave; }
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers.
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWaveSize - 1); }
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t bcast32(uint32_t v, int src) { return __shfl(v, src); }
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, int src)
+{
+    uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders this wave's earlier LDS / global writes before its later reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const uint32_t ln = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWaveSize; off <<= 1) {
+        uint32_t t = __shfl_up(v, off);
+        if (ln >= (uint32_t)off) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = kWaveSize / 2; off > 0; off >>= 1) {
+        uint32_t lo = __shfl_xor((uint32_t)v, off), hi = __shfl_xor((uint32_t)(v >> 32), off);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+// Exact wave-wide sum of per-lane u128 values; *ovf is set if the sum does
+// not fit in 128 bits.  Returned in every lane.
+__device__ u128 wave_sum_u128(u128 v, bool *ovf)
+{
+    uint64_t l0 = (uint64_t)(v & 0xffffffffu), l1 = (uint64_t)((v >> 32) & 0xffffffffu);
+    uint64_t l2 = (uint64_t)((v >> 64) & 0xffffffffu), l3 = (uint64_t)(v >> 96);
+    l0 = wave_sum_u64(l0);
+    l1 = wave_sum_u64(l1);
+    l2 = wave_sum_u64(l2);
+    l3 = wave_sum_u64(l3);
+    // each limb sum < 2^38
+    bool o = (l3 >> 32) != 0;
+    u128 t = (u128)l0;
+    o |= __builtin_add_overflow(t, (u128)l1 << 32, &t);
+    o |= __builtin_add_overflow(t, (u128)l2 << 64, &t);
+    o |= __builtin_add_overflow(t, (u128)(l3 & 0xffffffffu) << 96, &t);
+    *ovf = o;
+    return t;
+}
+
+// Adds v into a result slot with two 64-bit atomics; the carry out of the
+// low limb goes into the high limb, a carry out of the high limb is overflow.
+__device__ void slot_add(Slot *s, u128 v, bool ovf)
+{
+    const uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
+    bool over = ovf;
+    uint64_t add_hi = hi;
+    if (lo) {
+        unsigned long long old = atomicAdd(&s->lo, (unsigned long long)lo);
+        if ((uint64_t)old + lo < (uint64_t)old) {
+            add_hi += 1;
+            if (add_hi == 0) over = true;
+        }
+    }
+    if (add_hi) {
+        unsigned long long old = atomicAdd(&s->hi, (unsigned long long)add_hi);
+        if ((uint64_t)old + add_hi < (uint64_t)old) over = true;
+    }
+    if (over) atomicOr(&s->flags, FLAG_OVERFLOW);
+}
+
+// Wave-uniform flush of per-lane accumulators into a slot.
+__device__ void wave_flush(Slot *slots, uint32_t slot, u128 acc, bool ovf,
+                           unsigned long long pair_ops, unsigned long long filter_ops)
+{
+    bool o = false;
+    u128 tot = wave_sum_u128(acc, &o);
+    uint64_t any_ovf = __ballot(ovf);
+    if (lane_id() == 0) {
+        slot_add(&slots[slot], tot, o || any_ovf != 0);
+        if (pair_ops) atomicAdd(&slots[slot].pair_ops, pair_ops);
+        if (filter_ops) atomicAdd(&slots[slot].filter_ops, filter_ops);
+    }
+}
+
+// First index in [b, e) whose value is > key (values sorted ascending).
+__device__ __forceinline__ uint64_t upper_bound_u32(const uint32_t *a, uint64_t b, uint64_t e, uint32_t key)
+{
+    while (b < e) {
+        uint64_t mid = b + ((e - b) >> 1);
+        if (a[mid] <= key) b = mid + 1;
+        else e = mid;
+    }
+    return b;
+}
+
+// Largest j in [0, n) with prefix[j] <= x (prefix nondecreasing, prefix[0] == 0).
+__device__ __forceinline__ uint32_t find_segment(const uint64_t *prefix, uint32_t n, uint64_t x)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Slots.
+
+__global__ void k_fill_slots(Slot *slots, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        slots[i].lo = 0;
+        slots[i].hi = 0;
+        slots[i].flags = 0;
+        slots[i].pad = 0;
+        slots[i].pair_ops = 0;
+        slots[i].filter_ops = 0;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream)
+{
+    if (!n) return hipSuccess;
+    const uint64_t blocks = min((n + 255) / 256, (uint64_t)4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_slots(Slot *slots, uint32_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_slots, dim3((n + 255) / 256), dim3(256), 0, stream, slots, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// pA == 1: every root alone is an L; the count is sum_u C(d(u), qA).
+
+__global__ __launch_bounds__(kBlockThreads) void k_degree_sum(const Job *jobs, const uint32_t *job_ids,
+                                                              Slot *slots)
+{
+    const Job jb = jobs[job_ids[blockIdx.y]];
+    u128 acc = 0;
+    bool ovf = false;
+    for (uint64_t u = (uint64_t)jb.root_lo + blockIdx.x * blockDim.x + threadIdx.x; u < jb.root_hi;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t d = (uint32_t)(jb.ptrA[u + 1] - jb.ptrA[u]);
+        if (d >= jb.qA) {
+            if (d >= jb.n_ovf) ovf = true;
+            else ovf |= __builtin_add_overflow(acc, jb.binom[d], &acc);
+        }
+    }
+    wave_flush(slots, jb.slot, acc, ovf, 0, 0);
+}
+
+hipError_t launch_degree_sum(const Job *jobs, const uint32_t *job_ids, uint32_t n_jobs, Slot *slots,
+                             hipStream_t stream)
+{
+    if (n_jobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_degree_sum, dim3(64, n_jobs), dim3(kBlockThreads), 0, stream, jobs, job_ids, slots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Wedge scan shared by the two per-root kernels: for every neighbour v_j of u
+// (j = local id) and every w in N(v_j) with w > u, call f(j, w).  Waves take
+// the j's round robin; lanes stride over the oriented part of N(v_j).
+
+template <typename F>
+__device__ __forceinline__ void oriented_wedges(const Job &jb, uint32_t u, uint64_t ub, uint32_t du, F f)
+{
+    const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
+    for (uint32_t j = wv; j < du; j += kWavesPerBlock) {
+        const uint32_t v = jb.adjA[ub + j];
+        const uint64_t vb = jb.ptrB[v], ve = jb.ptrB[v + 1];
+        const uint64_t s = upper_bound_u32(jb.adjB, vb, ve, u);
+        for (uint64_t x = s + ln; x < ve; x += kWaveSize) f(j, jb.adjB[x]);
+    }
+}
+
+// k_cand_count: for every root of every job, k(u) = #{w > u : |N(u) n N(w)| >= qA}.
+// Common-neighbour counts live in a per-block dense counter array (all zero
+// between roots); the ids touched are listed so that only they are reset.
+__global__ __launch_bounds__(kBlockThreads) void k_cand_count(const Job *jobs, const uint64_t *job_root_prefix,
+                                                              uint32_t n_jobs, uint64_t total_roots,
+                                                              RootScratch sc, unsigned long long *queue,
+                                                              uint32_t *out_k, Slot *slots)
+{
+    __shared__ unsigned long long s_item;
+    __shared__ uint32_t s_nt, s_k;
+    uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
+    uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
+    const uint32_t tid = threadIdx.x;
+    u128 acc = 0;
+    bool ovf = false;
+    uint32_t cur_job = 0xffffffffu;
+    for (;;) {
+        if (tid == 0) {
+            s_item = atomicAdd(queue, 1ull);
+            s_nt = 0;
+            s_k = 0;
+        }
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= total_roots) break;
+        const uint32_t j = find_segment(job_root_prefix, n_jobs, item);
+        if (j != cur_job) {
+            if (cur_job != 0xffffffffu) wave_flush(slots, jobs[cur_job].slot, acc, ovf, 0, 0);
+            acc = 0;
+            ovf = false;
+            cur_job = j;
+        }
+        const Job jb = jobs[j];
+        const uint32_t u = jb.root_lo + (uint32_t)(item - job_root_prefix[j]);
+        const uint64_t ub = jb.ptrA[u];
+        const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - ub);
+        uint32_t k = 0;
+        if (du >= jb.qA) {
+            oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
+                if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
+            });
+            __syncthreads();
+            const uint32_t nt = s_nt;
+            for (uint32_t t = tid; t < nt; t += kBlockThreads) {
+                const uint32_t w = touched[t];
+                const uint32_t c = atomicExch(&cnt[w], 0u);
+                if (c >= jb.qA) {
+                    atomicAdd(&s_k, 1u);
+                    if (jb.pA == 2) {
+                        if (c >= jb.n_ovf) ovf = true;
+                        else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                    }
+                }
+            }
+            __syncthreads();
+            k = s_k;
+        }
+        if (tid == 0) out_k[item] = k;
+        __syncthreads();
+    }
+    if (cur_job != 0xffffffffu) wave_flush(slots, jobs[cur_job].slot, acc, ovf, 0, 0);
+}
+
+hipError_t launch_cand_count(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
+                             uint64_t total_roots, RootScratch scratch, uint32_t n_blocks,
+                             unsigned long long *queue, uint32_t *out_k, Slot *slots, hipStream_t stream)
+{
+    if (total_roots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cand_count, dim3(n_blocks), dim3(kBlockThreads), 0, stream, jobs, job_root_prefix,
+                       n_jobs, total_roots, scratch, queue, out_k, slots);
+    return hipGetLastError();
+}
+
+// Block-wide bitonic sort of s[0, n) ascending, n <= kSortCap; pads to a power of two.
+__device__ void block_sort_u32(uint32_t *s, uint32_t n)
+{
+    uint32_t n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    for (uint32_t i = n + threadIdx.x; i < n2; i += kBlockThreads) s[i] = 0xffffffffu;
+    __syncthreads();
+    for (uint32_t size = 2; size <= n2; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t pr = threadIdx.x; pr < (n2 >> 1); pr += kBlockThreads) {
+                const uint32_t i = 2 * stride * (pr / stride) + (pr % stride);
+                const uint32_t l = i + stride;
+                const bool asc = (i & size) == 0;
+                const uint32_t a = s[i], b = s[l];
+                if ((a > b) == asc) {
+                    s[i] = b;
+                    s[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// k_rows_build: candidate rows of every active root, column-major in the pool
+// (word w of row s at pool[off + w*k + s]), rows in increasing rank order of
+// the candidates whenever k <= kSortCap.
+__global__ __launch_bounds__(kBlockThreads) void k_rows_build(const Job *jobs, const ActiveRoot *roots,
+                                                              uint32_t n_roots, uint64_t *pool,
+                                                              RootScratch sc, unsigned long long *queue,
+                                                              Slot *slots)
+{
+    __shared__ unsigned long long s_item;
+    __shared__ uint32_t s_nt, s_k;
+    __shared__ uint32_t s_cand[kSortCap];
+    uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
+    uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
+    uint32_t *cand_g = sc.cand + (uint64_t)blockIdx.x * sc.stride;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            s_item = atomicAdd(queue, 1ull);
+            s_nt = 0;
+            s_k = 0;
+        }
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= n_roots) break;
+        const ActiveRoot ar = roots[item];
+        const Job jb = jobs[ar.job];
+        const uint32_t u = ar.root;
+        const uint64_t ub = jb.ptrA[u];
+        const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - ub);
+        const uint32_t W1 = (du + 63) >> 6;
+        const uint32_t kexp = ar.k;
+        uint64_t *base = pool + ar.pool_off;
+
+        oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
+            if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
+        });
+        __syncthreads();
+        const uint32_t nt = s_nt;
+        const bool in_lds = kexp <= (uint32_t)kSortCap;
+        uint32_t *cand = in_lds ? s_cand : cand_g;
+        for (uint32_t t = tid; t < nt; t += kBlockThreads) {
+            const uint32_t w = touched[t];
+            const uint32_t c = atomicAdd(&cnt[w], 0u);
+            if (c >= jb.qA) {
+                const uint32_t s = atomicAdd(&s_k, 1u);
+                if (s < kexp) cand[s] = w;
+            } else {
+                atomicExch(&cnt[w], 0u);
+            }
+        }
+        __syncthreads();
+        const uint32_t k = s_k;
+        if (k != kexp) {
+            // Cannot happen unless the two wedge passes disagree; leave the
+            // scratch clean and report.
+            for (uint32_t t = tid; t < nt; t += kBlockThreads) atomicExch(&cnt[touched[t]], 0u);
+            if (tid == 0) atomicOr(&slots[jb.slot].flags, FLAG_MISMATCH);
+            __syncthreads();
+            continue;
+        }
+        if (in_lds) block_sort_u32(s_cand, k);
+        __syncthreads();
+        for (uint32_t s = tid; s < k; s += kBlockThreads) atomicExch(&cnt[cand[s]], kSlotFlag | s);
+        const uint64_t words = (uint64_t)k * W1;
+        for (uint64_t x = tid; x < words; x += kBlockThreads) base[x] = 0;
+        __threadfence();
+        __syncthreads();
+        oriented_wedges(jb, u, ub, du, [&](uint32_t j, uint32_t w) {
+            const uint32_t e = atomicAdd(&cnt[w], 0u);
+            if (e & kSlotFlag) {
+                const uint32_t s = e & ~kSlotFlag;
+                atomicOr((unsigned long long *)&base[(uint64_t)(j >> 6) * k + s], 1ull << (j & 63));
+            }
+        });
+        __syncthreads();
+        for (uint32_t s = tid; s < k; s += kBlockThreads) atomicExch(&cnt[cand[s]], 0u);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t n_roots, uint64_t *pool,
+                             RootScratch scratch, uint32_t n_blocks, unsigned long long *queue, Slot *slots,
+                             hipStream_t stream)
+{
+    if (n_roots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows_build, dim3(n_blocks), dim3(kBlockThreads), 0, stream, jobs, roots, n_roots,
+                       pool, scratch, queue, slots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Enumeration.
+
+// Per-lane accumulation of one leaf value C(n, q).
+struct Acc {
+    u128 v;
+    bool ovf;
+};
+
+__device__ __forceinline__ void leaf_add(Acc &a, const u128 *binom, uint32_t n_ovf, uint32_t n)
+{
+    if (n >= n_ovf) {
+        a.ovf = true;
+        return;
+    }
+    a.ovf |= __builtin_add_overflow(a.v, binom[n], &a.v);
+}
+
+// sum over a < b < m of C(popcount(row_a & row_b), q).  Rows are column-major
+// in blk with the given stride; W words each, W <= WR held in registers.
+template <int WR>
+__device__ void pair_sum_reg(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W,
+                             const u128 *binom, uint32_t q, uint32_t n_ovf, Acc &acc)
+{
+    const uint32_t ln = lane_id();
+    for (uint32_t b0 = 1; b0 < m; b0 += kWaveSize) {
+        const uint32_t b = b0 + ln;
+        const bool valid = b < m;
+        uint64_t rb[WR];
+#pragma unroll
+        for (int w = 0; w < WR; ++w) rb[w] = (valid && (uint32_t)w < W) ? blk[(uint64_t)w * stride + b] : 0ull;
+        const uint32_t amax = min(m - 1, b0 + kWaveSize - 1);
+        for (uint32_t a = 0; a < amax; ++a) {
+            uint32_t n = 0;
+#pragma unroll
+            for (int w = 0; w < WR; ++w)
+                if ((uint32_t)w < W) n += __popcll(blk[(uint64_t)w * stride + a] & rb[w]);
+            if (valid && a < b && n >= q) leaf_add(acc, binom, n_ovf, n);
+        }
+    }
+}
+
+// Same sum for wide rows, read from memory word by word.
+__device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W,
+                             const u128 *binom, uint32_t q, uint32_t n_ovf, Acc &acc)
+{
+    const uint32_t ln = lane_id();
+    for (uint32_t b0 = 1; b0 < m; b0 += kWaveSize) {
+        const uint32_t b = b0 + ln;
+        const bool valid = b < m;
+        const uint32_t bb = valid ? b : 0;
+        const uint32_t amax = min(m - 1, b0 + kWaveSize - 1);
+        for (uint32_t a = 0; a < amax; ++a) {
+            uint32_t n = 0;
+            for (uint32_t w = 0; w < W; ++w)
+                n += __popcll(blk[(uint64_t)w * stride + a] & blk[(uint64_t)w * stride + bb]);
+            if (valid && a < b && n >= q) leaf_add(acc, binom, n_ovf, n);
+        }
+    }
+}
+
+__device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const u128 *binom,
+                         uint32_t q, uint32_t n_ovf, Acc &acc)
+{
+    if (m < 2) return;
+    if (W <= 1) pair_sum_reg<1>(blk, stride, m, W, binom, q, n_ovf, acc);
+    else if (W <= 2) pair_sum_reg<2>(blk, stride, m, W, binom, q, n_ovf, acc);
+    else if (W <= 4) pair_sum_reg<4>(blk, stride, m, W, binom, q, n_ovf, acc);
+    else if (W <= 8) pair_sum_reg<8>(blk, stride, m, W, binom, q, n_ovf, acc);
+    else pair_sum_mem(blk, stride, m, W, binom, q, n_ovf, acc);
+}
+
+// Children of row a: rows b > a whose AND with row a keeps >= q bits, written
+// (ANDed) into nblk (stride nstride) in order.  Returns their number.
+__device__ uint32_t filter_children(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t a, uint32_t W,
+                                    uint32_t q, uint64_t *nblk, uint32_t nstride)
+{
+    const uint32_t ln = lane_id();
+    uint32_t out = 0;
+    for (uint32_t b0 = a + 1; b0 < m; b0 += kWaveSize) {
+        const uint32_t b = b0 + ln;
+        const bool valid = b < m;
+        uint32_t n = 0;
+        if (valid)
+            for (uint32_t w = 0; w < W; ++w)
+                n += __popcll(blk[(uint64_t)w * stride + a] & blk[(uint64_t)w * stride + b]);
+        const bool keep = valid && n >= q;
+        const uint64_t mask = __ballot(keep);
+        if (keep) {
+            const uint32_t idx = out + mbcnt64(mask);
+            for (uint32_t w = 0; w < W; ++w)
+                nblk[(uint64_t)w * nstride + idx] = blk[(uint64_t)w * stride + a] & blk[(uint64_t)w * stride + b];
+        }
+        out += (uint32_t)__popcll(mask);
+    }
+    wave_sync();
+    return out;
+}
+
+// Wave-local bump allocator over the LDS and slab regions of one wavefront.
+struct Arena {
+    uint64_t *lds;
+    uint64_t *slab;
+    uint32_t lds_cap, lds_used;
+    uint64_t slab_cap, slab_used;
+};
+
+__device__ __forceinline__ uint64_t *arena_alloc(Arena &ar, uint64_t words, bool *fail)
+{
+    if (ar.lds_used + words <= ar.lds_cap) {
+        uint64_t *p = ar.lds + ar.lds_used;
+        ar.lds_used += (uint32_t)words;
+        return p;
+    }
+    if (ar.slab_used + words <= ar.slab_cap) {
+        uint64_t *p = ar.slab + ar.slab_used;
+        ar.slab_used += words;
+        return p;
+    }
+    *fail = true;
+    return nullptr;
+}
+
+// One (root, second vertex) task: the node {u, c_i} of the search tree.
+__device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const uint64_t *pool, Arena ar,
+                         uint64_t *stack, Acc &acc, unsigned long long &pair_ops,
+                         unsigned long long &filter_ops, bool *cap_fail)
+{
+    const uint32_t ln = lane_id();
+    const uint32_t u = rt.root;
+    const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - jb.ptrA[u]);
+    const uint32_t W1 = (du + 63) >> 6;
+    const uint32_t k = rt.k;
+    const uint64_t *base = pool + rt.pool_off;
+    const uint32_t q = jb.qA, pA = jb.pA;
+
+    // S2 = row i (common neighbours of u and c_i) and its word prefix counts.
+    uint64_t *s2 = arena_alloc(ar, 2ull * W1, cap_fail);
+    if (!s2) return;
+    uint64_t *pre = s2 + W1;
+    for (uint32_t w = ln; w < W1; w += kWaveSize) s2[w] = base[(uint64_t)w * k + i];
+    wave_sync();
+    uint32_t running = 0;
+    for (uint32_t w0 = 0; w0 < W1; w0 += kWaveSize) {
+        const uint32_t w = w0 + ln;
+        const uint32_t c = (w < W1) ? (uint32_t)__popcll(s2[w]) : 0u;
+        const uint32_t incl = wave_inclusive_scan(c);
+        if (w < W1) pre[w] = running + incl - c;
+        running += bcast32(incl, kWaveSize - 1);
+    }
+    wave_sync();
+    const uint32_t s2n = running;
+    const uint32_t W2 = (s2n + 63) >> 6;
+    const uint32_t rem = k - i - 1;
+    filter_ops += (unsigned long long)rem * W1;
+
+    if (pA == 3) {
+        // Leaves {u, c_i, c_b}: sum of C(|S2 n row_b|, q).
+        for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
+            const uint32_t b = b0 + ln;
+            if (b < k) {
+                uint32_t n = 0;
+                for (uint32_t w = 0; w < W1; ++w) n += __popcll(s2[w] & base[(uint64_t)w * k + b]);
+                if (n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
+            }
+        }
+        return;
+    }
+
+    // Level-2 block: rows b > i restricted to S2 and renumbered to S2's bits.
+    uint64_t *blk2 = arena_alloc(ar, (uint64_t)rem * W2, cap_fail);
+    if (!blk2) return;
+    uint32_t m2 = 0;
+    for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
+        const uint32_t b = b0 + ln;
+        const bool valid = b < k;
+        uint32_t n = 0;
+        if (valid)
+            for (uint32_t w = 0; w < W1; ++w) n += __popcll(s2[w] & base[(uint64_t)w * k + b]);
+        const bool keep = valid && n >= q;
+        const uint64_t mask = __ballot(keep);
+        if (keep) {
+            const uint32_t idx = m2 + mbcnt64(mask);
+            uint32_t ow = 0;
+            uint64_t cur = 0;
+            for (uint32_t w = 0; w < W1; ++w) {
+                const uint64_t sw = s2[w];
+                uint64_t bits = sw & base[(uint64_t)w * k + b];
+                const uint32_t p0 = (uint32_t)pre[w];
+                while (bits) {
+                    const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const uint32_t pos = p0 + (uint32_t)__popcll(sw & ((1ull << bt) - 1ull));
+                    const uint32_t tw = pos >> 6;
+                    while (ow < tw) {
+                        blk2[(uint64_t)ow * rem + idx] = cur;
+                        cur = 0;
+                        ++ow;
+                    }
+                    cur |= 1ull << (pos & 63);
+                }
+            }
+            while (ow < W2) {
+                blk2[(uint64_t)ow * rem + idx] = cur;
+                cur = 0;
+                ++ow;
+            }
+        }
+        m2 += (uint32_t)__popcll(mask);
+    }
+    wave_sync();
+    if (m2 < pA - 2) return;
+    if (pA == 4) {
+        pair_sum(blk2, rem, m2, W2, jb.binom, q, jb.n_ovf, acc);
+        pair_ops += (unsigned long long)m2 * (m2 - 1) / 2 * W2;
+        return;
+    }
+
+    // DFS over levels 2 .. pA-3; the node at level pA-2 is finished by pair_sum.
+    // stack[4*d + 0] = block offset (bit 63: in slab), [1] = stride | m << 32,
+    // [2] = cursor, [3] = arena marks (lds_used | slab_used << 32 when small).
+    auto enc_ptr = [&](const uint64_t *p) -> uint64_t {
+        return (p >= ar.lds && p < ar.lds + ar.lds_cap) ? (uint64_t)(p - ar.lds)
+                                                        : ((uint64_t)(p - ar.slab) | (1ull << 63));
+    };
+    auto dec_ptr = [&](uint64_t e) -> uint64_t * {
+        return (e >> 63) ? ar.slab + (e & ~(1ull << 63)) : ar.lds + e;
+    };
+    uint32_t d = 2;
+    stack[4 * 2 + 0] = enc_ptr(blk2);
+    stack[4 * 2 + 1] = (uint64_t)rem | ((uint64_t)m2 << 32);
+    stack[4 * 2 + 2] = 0;
+    stack[4 * 2 + 3] = 0;
+    for (;;) {
+        const uint64_t *blk = dec_ptr(stack[4 * d + 0]);
+        const uint32_t stride = (uint32_t)stack[4 * d + 1];
+        const uint32_t m = (uint32_t)(stack[4 * d + 1] >> 32);
+        const uint32_t a = (uint32_t)stack[4 * d + 2];
+        // row a needs pA - d - 1 more rows after it
+        if ((int64_t)a > (int64_t)m - (int64_t)pA + (int64_t)d) {
+            if (d == 2) break;
+            // pop: release this level's block
+            const uint64_t mk = stack[4 * d + 3];
+            ar.lds_used = (uint32_t)(mk & 0xffffffffu);
+            ar.slab_used = mk >> 32;
+            --d;
+            continue;
+        }
+        stack[4 * d + 2] = a + 1;
+        const uint32_t cap = m - a - 1;
+        const uint64_t mark = (uint64_t)ar.lds_used | (ar.slab_used << 32);
+        uint64_t *nb = arena_alloc(ar, (uint64_t)cap * W2, cap_fail);
+        if (!nb) return;
+        const uint32_t mc = filter_children(blk, stride, m, a, W2, q, nb, cap);
+        filter_ops += (unsigned long long)cap * W2;
+        if (mc >= pA - d - 1) {
+            if (d + 1 == pA - 2) {
+                pair_sum(nb, cap, mc, W2, jb.binom, q, jb.n_ovf, acc);
+                pair_ops += (unsigned long long)mc * (mc - 1) / 2 * W2;
+            } else {
+                ++d;
+                stack[4 * d + 0] = enc_ptr(nb);
+                stack[4 * d + 1] = (uint64_t)cap | ((uint64_t)mc << 32);
+                stack[4 * d + 2] = 0;
+                stack[4 * d + 3] = mark;
+                continue;
+            }
+        }
+        ar.lds_used = (uint32_t)(mark & 0xffffffffu);
+        ar.slab_used = mark >> 32;
+    }
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
+{
+    __shared__ uint64_t lds[kWavesPerBlock][kLdsWordsPerWave];
+    const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
+    const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    uint64_t *stack = &lds[wv][0];
+    Arena arena;
+    arena.lds = &lds[wv][kStackWords];
+    arena.lds_cap = (prm.lds_words > kStackWords ? min(prm.lds_words, kLdsWordsPerWave) : kStackWords) - kStackWords;
+    arena.lds_used = 0;
+    arena.slab = prm.slab + wave_global * prm.slab_words;
+    arena.slab_cap = prm.slab_words;
+    arena.slab_used = 0;
+
+    Acc acc;
+    acc.v = 0;
+    acc.ovf = false;
+    unsigned long long pair_ops = 0, filter_ops = 0;
+    uint32_t cur_job = 0xffffffffu;
+    for (;;) {
+        unsigned long long t = 0;
+        if (ln == 0) t = atomicAdd(prm.queue, 1ull);
+        t = bcast64(t, 0);
+        if (t >= prm.n_tasks) break;
+        // root owning task t: largest r with roots[r].task_begin <= t
+        uint32_t lo = 0, hi = prm.n_roots;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (prm.roots[mid].task_begin <= t) lo = mid;
+            else hi = mid;
+        }
+        const ActiveRoot rt = prm.roots[lo];
+        if (rt.job != cur_job) {
+            if (cur_job != 0xffffffffu)
+                wave_flush(prm.slots, prm.jobs[cur_job].slot, acc.v, acc.ovf, pair_ops, filter_ops);
+            acc.v = 0;
+            acc.ovf = false;
+            pair_ops = 0;
+            filter_ops = 0;
+            cur_job = rt.job;
+        }
+        const Job jb = prm.jobs[rt.job];
+        bool cap_fail = false;
+        run_task(jb, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, acc, pair_ops, filter_ops,
+                 &cap_fail);
+        if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
+    }
+    if (cur_job != 0xffffffffu)
+        wave_flush(prm.slots, prm.jobs[cur_job].slot, acc.v, acc.ovf, prm.instrument ? pair_ops : 0,
+                   prm.instrument ? filter_ops : 0);
+}
+
+hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream)
+{
+    if (prm.n_tasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_enumerate, dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
+    return hipGetLastError();
+}
+
+}  // namespace bcdev

@@ -1,0 +1,94 @@
+"""The C-ABI library loads on any host and exports every function declared in
+include/bc.h; argument and CSR validation happen before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bc.h")
+
+
+@pytest.fixture(scope="module")
+def bc():
+    from paper_2403_07858_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+    from paper_2403_07858_amd import bc as m
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("bc_build", "bc_count", "bc_count_roots", "bc_count_batch", "bc_free", "bc_status_string",
+                 "bc_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(bc):
+    lib = ctypes.CDLL(bc.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(bc.EXPORTED) <= set(declared_functions())
+
+
+def test_status_strings(bc):
+    assert bc.bc_status_string(0) == "BC_OK"
+    assert bc.bc_status_string(bc.BC_E_OVERFLOW) == "BC_E_OVERFLOW"
+    assert bc.bc_status_string(-1234) == "BC_E_UNKNOWN"
+
+
+def _u(x):
+    return np.array(x, dtype=np.uint64)
+
+
+def _i(x):
+    return np.array(x, dtype=np.uint32)
+
+
+def test_duplicate_edge_rejected(bc):
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_build(2, 2, _u([0, 2, 3]), _i([0, 0, 1]), _u([0, 2, 3]), _i([0, 0, 1]))
+    assert e.value.status == bc.BC_E_BAD_CSR
+
+
+def test_out_of_range_id_rejected(bc):
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_build(1, 2, _u([0, 1]), _i([7]), _u([0, 0, 1]), _i([0]))
+    assert e.value.status == bc.BC_E_BAD_CSR
+
+
+def test_bad_indptr_rejected(bc):
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_build(2, 2, _u([0, 2, 1]), _i([0, 1]), _u([0, 1, 2]), _i([0, 0]))
+    assert e.value.status == bc.BC_E_BAD_CSR
+
+
+def test_non_transpose_rejected(bc):
+    # U says 0-0, 1-1; V says 0-1, 1-0
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_build(2, 2, _u([0, 1, 2]), _i([0, 1]), _u([0, 1, 2]), _i([1, 0]))
+    assert e.value.status == bc.BC_E_INCONSISTENT
+    # same degrees on both sides, different edges: U has 0-0, 1-1; V has 0-1, 1-0
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_build(2, 3, _u([0, 1, 2]), _i([0, 1]), _u([0, 1, 2, 2]), _i([1, 0]))
+    assert e.value.status == bc.BC_E_INCONSISTENT
+
+
+def test_null_and_range_arguments(bc):
+    lib = bc._lib
+    out = bc.bc_u128()
+    assert lib.bc_count(None, 2, 2, None, ctypes.byref(out), None) == bc.BC_E_INVALID_ARG
+    assert lib.bc_build(None, None, None, None) == bc.BC_E_INVALID_ARG
+    assert lib.bc_count_roots(None, 2, 2, 0, 0, 1, None, ctypes.byref(out), None) == bc.BC_E_INVALID_ARG
+    assert lib.bc_graph_info(None, None, None, None) == bc.BC_E_INVALID_ARG
+    lib.bc_free(None)  # NULL is ignored
+    assert out.lo == 0 and out.hi == 0
