@@ -37,7 +37,7 @@ enum {
     BC_E_DEVICE = -5,        /* a HIP runtime error; the HIP message is in bc_last_error() */
     BC_E_OVERFLOW = -6,      /* the count needs more than 128 bits */
     BC_E_REJECTED = -7,      /* server: query refused by admission control */
-    BC_E_TIMEOUT = -8,       /* server: deadline passed before the query ran */
+    BC_E_TIMEOUT = -8,       /* the time limit or deadline passed before the count finished */
     BC_E_CANCELLED = -9,     /* server: shut down before the query ran */
     BC_E_PENDING = -10,      /* server: non-blocking poll, result not ready yet */
     BC_E_NOT_FOUND = -11     /* server: unknown ticket or graph id */
@@ -68,6 +68,8 @@ typedef struct {
     uint32_t lds_words;        /* per-wavefront LDS budget in 64-bit words; 0 = default */
     uint32_t waves_per_cu;     /* persistent-grid occupancy target; 0 = default */
     uint32_t instrument;       /* nonzero: fill the work counters of bc_stats */
+    uint32_t timeout_ms;       /* device-side time limit of the call (0 = none); past it the
+                                  call fails with BC_E_TIMEOUT and no count is returned */
 } bc_opts;
 
 /* Timings (milliseconds, measured with HIP events on the stream) and work

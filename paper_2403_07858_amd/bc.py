@@ -50,7 +50,7 @@ class bc_csr(ctypes.Structure):
 class bc_opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("stream", ctypes.c_void_p), ("anchor", ctypes.c_int32),
                 ("lds_words", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
-                ("instrument", ctypes.c_uint32)]
+                ("instrument", ctypes.c_uint32), ("timeout_ms", ctypes.c_uint32)]
 
 
 class bc_stats(ctypes.Structure):
@@ -122,7 +122,8 @@ def _stream_handle(stream):
     return int(h)
 
 
-def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, instrument=False) -> bc_opts:
+def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, instrument=False,
+              timeout_ms=0) -> bc_opts:
     o = bc_opts()
     o.struct_size = ctypes.sizeof(bc_opts)
     o.stream = _stream_handle(stream)
@@ -130,6 +131,7 @@ def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, i
     o.lds_words = lds_words
     o.waves_per_cu = waves_per_cu
     o.instrument = 1 if instrument else 0
+    o.timeout_ms = timeout_ms
     return o
 
 
@@ -236,3 +238,114 @@ def bc_count_batch(graphs, ps, qs, **opt):
     if s != BC_OK:
         raise BCError(s, "bc_count_batch")
     return [out[i].value for i in range(n)], [int(x) for x in st[:n]]
+
+
+# ---------------------------------------------------------------------------
+# Counting service (include/bc_server.h).
+
+class bc_server_opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("max_pending", ctypes.c_uint32),
+                ("memory_budget_bytes", ctypes.c_uint64), ("batch_timeout_ms", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
+class bc_query_stats(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("batch_id", ctypes.c_uint64), ("batch_size", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
+class bc_server_summary(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("timed_out", ctypes.c_uint64), ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("qps", ctypes.c_double), ("mean_batch", ctypes.c_double), ("max_overlap", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
+def _bind_server():
+    P, I32, U32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "bc_server_create": ([P, P], I32),
+        "bc_server_add_graph": ([P, P, P], I32),
+        "bc_server_submit": ([P, U32, U32, U32, U64, P], I32),
+        "bc_server_poll": ([P, U64, ctypes.c_int, P, P], I32),
+        "bc_server_stats": ([P, P], I32),
+        "bc_server_now_ns": ([], U64),
+        "bc_server_destroy": ([P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(_lib, name)
+        f.argtypes = args
+        f.restype = res
+
+
+_bind_server()
+EXPORTED = EXPORTED + ("bc_server_create", "bc_server_add_graph", "bc_server_submit", "bc_server_poll",
+                       "bc_server_stats", "bc_server_now_ns", "bc_server_destroy")
+
+
+class Server:
+    """Thin wrapper of a ``bc_server *``; graphs must outlive it."""
+
+    def __init__(self, max_inflight=2, max_batch=256, max_pending=0, memory_budget_bytes=0, batch_timeout_ms=0):
+        o = bc_server_opts()
+        o.struct_size = ctypes.sizeof(bc_server_opts)
+        o.max_inflight, o.max_batch, o.max_pending = max_inflight, max_batch, max_pending
+        o.memory_budget_bytes, o.batch_timeout_ms = memory_budget_bytes, batch_timeout_ms
+        h = ctypes.c_void_p()
+        s = _lib.bc_server_create(ctypes.byref(o), ctypes.byref(h))
+        if s != BC_OK:
+            raise BCError(s, "bc_server_create")
+        self.handle = h.value
+        self._graphs = []
+
+    def add_graph(self, g: Graph) -> int:
+        gid = ctypes.c_uint32()
+        s = _lib.bc_server_add_graph(self.handle, g.handle, ctypes.byref(gid))
+        if s != BC_OK:
+            raise BCError(s, "bc_server_add_graph")
+        self._graphs.append(g)
+        return gid.value
+
+    def submit(self, graph_id: int, p: int, q: int, deadline_ns: int = 0) -> int:
+        """Ticket id, or raises BCError (e.g. BC_E_REJECTED)."""
+        t = ctypes.c_uint64()
+        s = _lib.bc_server_submit(self.handle, graph_id, p, q, deadline_ns, ctypes.byref(t))
+        if s != BC_OK:
+            raise BCError(s, "bc_server_submit")
+        return t.value
+
+    def poll(self, ticket: int, block: bool = True):
+        """(status, count or None, stats dict)."""
+        out, st = bc_u128(), bc_query_stats()
+        s = _lib.bc_server_poll(self.handle, ticket, 1 if block else 0, ctypes.byref(out), ctypes.byref(st))
+        return s, (out.value if s == BC_OK else None), st.as_dict()
+
+    def stats(self) -> dict:
+        st = bc_server_summary()
+        s = _lib.bc_server_stats(self.handle, ctypes.byref(st))
+        if s != BC_OK:
+            raise BCError(s, "bc_server_stats")
+        return st.as_dict()
+
+    @staticmethod
+    def now_ns() -> int:
+        return _lib.bc_server_now_ns()
+
+    def close(self):
+        if self.handle:
+            _lib.bc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbc.so")
-SOURCES = ["bc_kernels.hip", "bc_host.cpp"]
+SOURCES = ["bc_kernels.hip", "bc_host.cpp", "bc_server.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

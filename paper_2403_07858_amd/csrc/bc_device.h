@@ -25,6 +25,7 @@ struct Job {
     uint32_t n_ovf;         // smallest n with C(n, qA) >= 2^128 (binom_n if none)
     uint32_t slot;          // result slot
     uint32_t pad;
+    uint64_t deadline;      // device real-time clock tick after which the job gives up (0 = none)
 };
 
 // One root that owns enumeration tasks, in schedule (cost) order.
@@ -49,6 +50,7 @@ enum : unsigned {
     FLAG_OVERFLOW = 1u,     // count does not fit in 128 bits
     FLAG_CAPACITY = 2u,     // a scratch bound computed on the host was exceeded
     FLAG_MISMATCH = 4u,     // candidate count differs between the two wedge passes
+    FLAG_TIMEOUT = 8u,      // the job's deadline passed before it finished
 };
 
 constexpr int kWaveSize = 64;
@@ -94,5 +96,8 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
 hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream);
 
 uint32_t max_lds_words_per_wave();
+
+// Reads the device real-time clock (s_memrealtime) into *out (device memory).
+hipError_t launch_read_clock(uint64_t *out, hipStream_t stream);
 
 }  // namespace bcdev

@@ -4,6 +4,7 @@
 #include "bc.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "bc_device.h"
+#include "bc_internal.h"
 
 using bcdev::u128;
 
@@ -291,7 +293,54 @@ struct JobSpec {
     int32_t anchor;            // requested (AUTO allowed)
     uint64_t rank_lo, rank_hi; // only used when ranged
     bool ranged;
+    uint64_t deadline_ns;      // steady clock, 0 = none
 };
+
+// Device real-time clock against the host steady clock, per device: two
+// samples 20 ms apart give the tick rate, the second one the offset.
+struct ClockCal {
+    bool ok = false;
+    double ticks_per_ns = 0.1;
+    double offset = 0.0;
+};
+
+bc_status device_clock(int device, hipStream_t st, ClockCal &out)
+{
+    static std::mutex mu;
+    static std::vector<ClockCal> cache(64);
+    std::lock_guard<std::mutex> g(mu);
+    if (device < 0 || device >= 64) return set_error(BC_E_DEVICE, "device id out of range");
+    if (cache[device].ok) {
+        out = cache[device];
+        return BC_OK;
+    }
+    uint64_t *d = nullptr;
+    BC_HIP(hipMalloc(&d, 8));
+    double mid[2];
+    uint64_t tick[2];
+    for (int i = 0; i < 2; ++i) {
+        if (i) std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        uint64_t t0 = bcint::steady_ns();
+        hipError_t e = bcdev::launch_read_clock(d, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&tick[i], d, 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        uint64_t t1 = bcint::steady_ns();
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_error(e, "clock calibration");
+        }
+        mid[i] = 0.5 * ((double)t0 + (double)t1);
+    }
+    (void)hipFree(d);
+    ClockCal c;
+    c.ok = true;
+    c.ticks_per_ns = (double)(tick[1] - tick[0]) / (mid[1] - mid[0]);
+    if (!(c.ticks_per_ns > 0)) c.ticks_per_ns = 0.1;   // nominal 100 MHz
+    c.offset = (double)tick[1] - c.ticks_per_ns * mid[1];
+    cache[device] = c;
+    out = c;
+    return BC_OK;
+}
 
 // C(n, q) for n in [0, nmax] as exact u128; n_ovf = first n that overflows.
 void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n_ovf)
@@ -438,6 +487,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     const uint32_t nj = (uint32_t)jobs.size();
 
     // 2. Device job table and binomial columns.
+    ClockCal clock;
     std::vector<bcdev::Job> hjobs(nj);
     std::vector<uint64_t> tab_off(nj + 1, 0);
     std::vector<std::vector<u128>> cols(nj);
@@ -462,6 +512,15 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         d.binom_n = A.max_deg + 1;
         d.n_ovf = n_ovf;
         d.slot = j;
+        d.deadline = 0;
+        const uint64_t dl = specs[hj.spec].deadline_ns;
+        if (dl) {
+            if (!clock.ok) {
+                if (bc_status e = device_clock(device, st, clock)) return e;
+            }
+            const double t = clock.offset + clock.ticks_per_ns * (double)dl;
+            d.deadline = t < 1.0 ? 1ull : (uint64_t)t;
+        }
         tab_off[j + 1] = tab_off[j] + cols[j].size();
     }
     DevAlloc mem(st);
@@ -659,7 +718,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             out[i] = bc_u128{0, 0};
             continue;
         }
-        if (s.flags & bcdev::FLAG_OVERFLOW) {
+        if (s.flags & bcdev::FLAG_TIMEOUT) {
+            item_status[i] = BC_E_TIMEOUT;
+            g_last_error = "time limit reached before the count finished";
+        } else if (s.flags & bcdev::FLAG_OVERFLOW) {
             item_status[i] = BC_E_OVERFLOW;
             g_last_error = "count exceeds 128 bits";
         } else if (s.flags & (bcdev::FLAG_CAPACITY | bcdev::FLAG_MISMATCH)) {
@@ -693,6 +755,12 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     return overall;
 }
 
+uint64_t opts_deadline(const bc_opts *o)
+{
+    if (!o || o->struct_size < offsetof(bc_opts, timeout_ms) + sizeof(uint32_t) || o->timeout_ms == 0) return 0;
+    return bcint::steady_ns() + (uint64_t)o->timeout_ms * 1000000ull;
+}
+
 bc_status check_pq(uint32_t p, uint32_t q)
 {
     if (p < 1 || q < 1 || p > 32 || q > 32) return set_error(BC_E_INVALID_ARG, "p and q must be in 1..32");
@@ -708,7 +776,7 @@ extern "C" bc_status bc_count(const bc_graph *g, uint32_t p, uint32_t q, const b
     if (!g || !out) return set_error(BC_E_INVALID_ARG, "bc_count: NULL argument");
     if (bc_status s = check_pq(p, q)) return s;
     if (bc_status s = check_opts(opts)) return s;
-    std::vector<JobSpec> sp{JobSpec{g, p, q, opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false}};
+    std::vector<JobSpec> sp{JobSpec{g, p, q, opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false, opts_deadline(opts)}};
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
     bc_status s = run_jobs(sp, opts, res, ist, st);
@@ -728,7 +796,7 @@ extern "C" bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, i
     if (anchor != BC_ANCHOR_U && anchor != BC_ANCHOR_V)
         return set_error(BC_E_INVALID_ARG, "bc_count_roots: anchor must be BC_ANCHOR_U or BC_ANCHOR_V");
     if (rank_lo > rank_hi) return set_error(BC_E_INVALID_ARG, "bc_count_roots: rank_lo > rank_hi");
-    std::vector<JobSpec> sp{JobSpec{g, p, q, anchor, rank_lo, rank_hi, true}};
+    std::vector<JobSpec> sp{JobSpec{g, p, q, anchor, rank_lo, rank_hi, true, opts_deadline(opts)}};
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
     bc_status s = run_jobs(sp, opts, res, ist, st);
@@ -747,6 +815,7 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
     if (bc_status s = check_opts(opts)) return s;
     std::vector<JobSpec> sp;
     std::vector<size_t> idx;
+    const uint64_t dl = opts_deadline(opts);
     for (size_t i = 0; i < n; ++i) {
         if (!graphs[i] || p[i] < 1 || q[i] < 1 || p[i] > 32 || q[i] > 32) {
             item_status[i] = BC_E_INVALID_ARG;
@@ -756,7 +825,7 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
             return set_error(BC_E_INVALID_ARG, "bc_count_batch: graphs on different devices");
         item_status[i] = BC_OK;
         idx.push_back(i);
-        sp.push_back(JobSpec{graphs[i], p[i], q[i], opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false});
+        sp.push_back(JobSpec{graphs[i], p[i], q[i], opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false, dl});
     }
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
@@ -768,6 +837,53 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
     }
     return s;
 }
+
+namespace bcint {
+
+uint64_t steady_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 *out, bc_status *status)
+{
+    std::vector<JobSpec> sp;
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < n; ++i) {
+        if (!qs[i].g || qs[i].p < 1 || qs[i].q < 1 || qs[i].p > 32 || qs[i].q > 32) {
+            status[i] = BC_E_INVALID_ARG;
+            out[i] = bc_u128{0, 0};
+            continue;
+        }
+        idx.push_back(i);
+        sp.push_back(JobSpec{qs[i].g, qs[i].p, qs[i].q, BC_ANCHOR_AUTO, 0, 0, false, qs[i].deadline_ns});
+    }
+    std::vector<bc_u128> res;
+    std::vector<bc_status> ist;
+    bc_status s = run_jobs(sp, opts, res, ist, nullptr);
+    for (size_t t = 0; t < idx.size(); ++t) {
+        status[idx[t]] = (s == BC_OK || s == BC_E_DEVICE) && t < ist.size() ? ist[t] : s;
+        out[idx[t]] = (status[idx[t]] == BC_OK && t < res.size()) ? res[t] : bc_u128{0, 0};
+    }
+    return s;
+}
+
+uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q)
+{
+    // candidate-pass scratch (3 u32 arrays per block over the anchor side),
+    // the per-root rows (bounded by 16 B per edge in practice) and a share of
+    // the enumeration slabs.
+    (void)q;
+    const uint64_t n = std::max(g->side[0].n, g->side[1].n);
+    const uint64_t blocks = 2ull * 256;
+    return blocks * n * 12 + 16 * g->nnz + (uint64_t)std::max<uint32_t>(p, 1) * (64ull << 20);
+}
+
+int graph_device(const bc_graph *g) { return g->device; }
+
+}  // namespace bcint
 
 extern "C" const char *bc_status_string(bc_status s)
 {

@@ -129,6 +129,26 @@ __device__ void wave_flush(Slot *slots, uint32_t slot, u128 acc, bool ovf,
     }
 }
 
+// True once the device real-time clock has passed a nonzero deadline.
+__device__ __forceinline__ bool past_deadline(uint64_t deadline)
+{
+    if (deadline == 0) return false;
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    // wave-uniform by construction (scalar clock read); make it explicit
+    return __builtin_amdgcn_readfirstlane((uint32_t)(now > deadline)) != 0u;
+}
+
+__global__ void k_read_clock(uint64_t *out)
+{
+    if (threadIdx.x == 0) out[0] = __builtin_amdgcn_s_memrealtime();
+}
+
+hipError_t launch_read_clock(uint64_t *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_read_clock, dim3(1), dim3(64), 0, stream, out);
+    return hipGetLastError();
+}
+
 // First index in [b, e) whose value is > key (values sorted ascending).
 __device__ __forceinline__ uint64_t upper_bound_u32(const uint32_t *a, uint64_t b, uint64_t e, uint32_t key)
 {
@@ -243,7 +263,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_cand_count(const Job *jobs, c
                                                               uint32_t *out_k, Slot *slots)
 {
     __shared__ unsigned long long s_item;
-    __shared__ uint32_t s_nt, s_k;
+    __shared__ uint32_t s_nt, s_k, s_late;
     uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
     uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
     const uint32_t tid = threadIdx.x;
@@ -271,7 +291,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_cand_count(const Job *jobs, c
         const uint64_t ub = jb.ptrA[u];
         const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - ub);
         uint32_t k = 0;
-        if (du >= jb.qA) {
+        // one thread reads the clock so that the whole block takes the same branch
+        if (tid == 0) {
+            s_late = past_deadline(jb.deadline) ? 1u : 0u;
+            if (s_late) atomicOr(&slots[jb.slot].flags, FLAG_TIMEOUT);
+        }
+        __syncthreads();
+        const bool late = s_late != 0;
+        if (du >= jb.qA && !late) {
             oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
                 if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
             });
@@ -340,7 +367,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_build(const Job *jobs, c
                                                               Slot *slots)
 {
     __shared__ unsigned long long s_item;
-    __shared__ uint32_t s_nt, s_k;
+    __shared__ uint32_t s_nt, s_k, s_late;
     __shared__ uint32_t s_cand[kSortCap];
     uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
     uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
@@ -357,6 +384,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_build(const Job *jobs, c
         if (item >= n_roots) break;
         const ActiveRoot ar = roots[item];
         const Job jb = jobs[ar.job];
+        // one thread reads the clock so that the whole block takes the same branch
+        if (tid == 0) {
+            s_late = past_deadline(jb.deadline) ? 1u : 0u;
+            if (s_late) atomicOr(&slots[jb.slot].flags, FLAG_TIMEOUT);
+        }
+        __syncthreads();
+        if (s_late) {
+            // rows stay unwritten; the enumeration sees the same passed deadline
+            __syncthreads();
+            continue;
+        }
         const uint32_t u = ar.root;
         const uint64_t ub = jb.ptrA[u];
         const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - ub);
@@ -547,7 +585,7 @@ __device__ __forceinline__ uint64_t *arena_alloc(Arena &ar, uint64_t words, bool
 // One (root, second vertex) task: the node {u, c_i} of the search tree.
 __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const uint64_t *pool, Arena ar,
                          uint64_t *stack, Acc &acc, unsigned long long &pair_ops,
-                         unsigned long long &filter_ops, bool *cap_fail)
+                         unsigned long long &filter_ops, bool *cap_fail, bool *timed_out)
 {
     const uint32_t ln = lane_id();
     const uint32_t u = rt.root;
@@ -655,6 +693,10 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
     stack[4 * 2 + 2] = 0;
     stack[4 * 2 + 3] = 0;
     for (;;) {
+        if (past_deadline(jb.deadline)) {
+            *timed_out = true;
+            return;
+        }
         const uint64_t *blk = dec_ptr(stack[4 * d + 0]);
         const uint32_t stride = (uint32_t)stack[4 * d + 1];
         const uint32_t m = (uint32_t)(stack[4 * d + 1] >> 32);
@@ -736,10 +778,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
             cur_job = rt.job;
         }
         const Job jb = prm.jobs[rt.job];
-        bool cap_fail = false;
-        run_task(jb, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, acc, pair_ops, filter_ops,
-                 &cap_fail);
+        bool cap_fail = false, timed_out = past_deadline(jb.deadline);
+        if (!timed_out)
+            run_task(jb, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, acc, pair_ops, filter_ops,
+                     &cap_fail, &timed_out);
         if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
+        if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
     }
     if (cur_job != 0xffffffffu)
         wave_flush(prm.slots, prm.jobs[cur_job].slot, acc.v, acc.ovf, prm.instrument ? pair_ops : 0,

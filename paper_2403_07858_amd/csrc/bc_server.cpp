@@ -1,0 +1,308 @@
+// Counting service over device-resident graphs: memory-admitted continuous
+// batching (include/bc_server.h).  Worker threads each own a HIP stream and
+// run one batch at a time through the batched device path; several workers
+// keep several batches in flight, so new queries join the device while
+// earlier ones are still running.
+#include "bc_server.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "bc_internal.h"
+
+namespace {
+
+struct Ticket {
+    uint32_t gid, p, q;
+    uint64_t deadline_ns;
+    uint64_t est_bytes;
+    uint64_t t_submit, t_start, t_done;
+    bc_status status;
+    bc_u128 value;
+    bool done;
+    uint64_t batch_id;
+    uint32_t batch_size;
+};
+
+}  // namespace
+
+struct bc_server {
+    bc_server_opts opts{};
+    std::vector<const bc_graph *> graphs;
+    std::mutex mu;
+    std::condition_variable cv_work;   // pending queue or budget changed
+    std::condition_variable cv_done;   // some ticket finished
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    uint64_t next_ticket = 1;
+    uint64_t next_batch = 1;
+    uint64_t inflight_bytes = 0;
+    uint32_t inflight_batches = 0;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    // statistics
+    uint64_t submitted = 0, completed = 0, rejected = 0, timed_out = 0, failed = 0, batches = 0, batched_queries = 0;
+    uint32_t max_overlap = 0;
+    std::vector<double> latencies_ms;
+    uint64_t t_created = 0;
+};
+
+namespace {
+
+void finish(bc_server *s, Ticket &t, bc_status st, bc_u128 v, uint64_t now)
+{
+    t.status = st;
+    t.value = v;
+    t.done = true;
+    t.t_done = now;
+    if (st == BC_OK) {
+        s->completed++;
+        s->latencies_ms.push_back((double)(now - t.t_submit) / 1e6);
+    } else if (st == BC_E_TIMEOUT) {
+        s->timed_out++;
+    } else if (st != BC_E_CANCELLED) {
+        s->failed++;
+    }
+}
+
+void worker_main(bc_server *s)
+{
+    hipStream_t stream = nullptr;
+    if (!s->graphs.empty()) (void)hipSetDevice(bcint::graph_device(s->graphs[0]));
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    const uint32_t max_batch = s->opts.max_batch ? s->opts.max_batch : 256;
+    for (;;) {
+        std::vector<uint64_t> batch;
+        uint64_t batch_bytes = 0, batch_id = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (;;) {
+                if (s->stop) break;
+                // drop queries whose deadline passed while they waited
+                const uint64_t now = bcint::steady_ns();
+                for (auto it = s->pending.begin(); it != s->pending.end();) {
+                    Ticket &t = s->tickets[*it];
+                    if (t.deadline_ns && now >= t.deadline_ns) {
+                        finish(s, t, BC_E_TIMEOUT, bc_u128{0, 0}, now);
+                        it = s->pending.erase(it);
+                        s->cv_done.notify_all();
+                    } else {
+                        ++it;
+                    }
+                }
+                // admit in arrival order while the memory budget allows
+                while (!s->pending.empty() && batch.size() < max_batch) {
+                    Ticket &t = s->tickets[s->pending.front()];
+                    if (s->inflight_bytes + batch_bytes + t.est_bytes > s->opts.memory_budget_bytes) break;
+                    batch_bytes += t.est_bytes;
+                    batch.push_back(s->pending.front());
+                    s->pending.pop_front();
+                }
+                if (!batch.empty()) break;
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            }
+            if (s->stop && batch.empty()) break;
+            if (s->stop) {
+                // shutting down: hand the batch back as cancelled
+                const uint64_t now = bcint::steady_ns();
+                for (uint64_t id : batch) finish(s, s->tickets[id], BC_E_CANCELLED, bc_u128{0, 0}, now);
+                s->cv_done.notify_all();
+                break;
+            }
+            s->inflight_bytes += batch_bytes;
+            s->inflight_batches++;
+            s->max_overlap = std::max(s->max_overlap, s->inflight_batches);
+            batch_id = s->next_batch++;
+            s->batches++;
+            s->batched_queries += batch.size();
+        }
+        // run the batch outside the lock
+        std::vector<bcint::Query> qs(batch.size());
+        const uint64_t t_start = bcint::steady_ns();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < batch.size(); ++i) {
+                Ticket &t = s->tickets[batch[i]];
+                t.t_start = t_start;
+                qs[i] = bcint::Query{s->graphs[t.gid], t.p, t.q, t.deadline_ns};
+                if (s->opts.batch_timeout_ms) {
+                    const uint64_t cap = t_start + (uint64_t)s->opts.batch_timeout_ms * 1000000ull;
+                    if (qs[i].deadline_ns == 0 || cap < qs[i].deadline_ns) qs[i].deadline_ns = cap;
+                }
+            }
+        }
+        std::vector<bc_u128> out(batch.size());
+        std::vector<bc_status> st(batch.size(), BC_OK);
+        bc_opts o{};
+        o.struct_size = sizeof(bc_opts);
+        o.stream = stream;
+        o.anchor = BC_ANCHOR_AUTO;
+        bc_status rc = bcint::count_queries(qs.data(), qs.size(), &o, out.data(), st.data());
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            const uint64_t now = bcint::steady_ns();
+            for (size_t i = 0; i < batch.size(); ++i) {
+                Ticket &t = s->tickets[batch[i]];
+                t.batch_id = batch_id;
+                t.batch_size = (uint32_t)batch.size();
+                finish(s, t, (rc == BC_OK || rc == BC_E_DEVICE) ? st[i] : rc, out[i], now);
+            }
+            s->inflight_bytes -= batch_bytes;
+            s->inflight_batches--;
+        }
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace
+
+extern "C" bc_status bc_server_create(const bc_server_opts *opts, bc_server **out)
+{
+    if (!out) return BC_E_INVALID_ARG;
+    bc_server *s = new (std::nothrow) bc_server();
+    if (!s) return BC_E_OOM;
+    if (opts) s->opts = *opts;
+    if (!s->opts.max_inflight) s->opts.max_inflight = 2;
+    if (s->opts.max_inflight > 16) s->opts.max_inflight = 16;
+    if (!s->opts.max_batch) s->opts.max_batch = 256;
+    if (!s->opts.max_pending) s->opts.max_pending = 65536;
+    if (!s->opts.memory_budget_bytes) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) free_b = 8ull << 30;
+        s->opts.memory_budget_bytes = free_b / 2;
+    }
+    s->t_created = bcint::steady_ns();
+    *out = s;
+    return BC_OK;
+}
+
+extern "C" bc_status bc_server_add_graph(bc_server *s, const bc_graph *g, uint32_t *graph_id)
+{
+    if (!s || !g || !graph_id) return BC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->graphs.empty() && bcint::graph_device(g) != bcint::graph_device(s->graphs[0])) return BC_E_INVALID_ARG;
+    *graph_id = (uint32_t)s->graphs.size();
+    s->graphs.push_back(g);
+    // workers start with the first graph (they bind to its device)
+    if (s->workers.empty())
+        for (uint32_t i = 0; i < s->opts.max_inflight; ++i) s->workers.emplace_back(worker_main, s);
+    return BC_OK;
+}
+
+extern "C" bc_status bc_server_submit(bc_server *s, uint32_t graph_id, uint32_t p, uint32_t q, uint64_t deadline_ns,
+                                      uint64_t *ticket)
+{
+    if (!s || !ticket) return BC_E_INVALID_ARG;
+    if (p < 1 || q < 1 || p > 32 || q > 32) return BC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id >= s->graphs.size()) return BC_E_NOT_FOUND;
+    s->submitted++;
+    Ticket t{};
+    t.gid = graph_id;
+    t.p = p;
+    t.q = q;
+    t.deadline_ns = deadline_ns;
+    t.est_bytes = bcint::estimate_scratch_bytes(s->graphs[graph_id], p, q);
+    t.t_submit = bcint::steady_ns();
+    t.done = false;
+    if (t.est_bytes > s->opts.memory_budget_bytes || s->pending.size() >= s->opts.max_pending) {
+        s->rejected++;
+        return BC_E_REJECTED;
+    }
+    const uint64_t id = s->next_ticket++;
+    s->tickets.emplace(id, t);
+    s->pending.push_back(id);
+    *ticket = id;
+    s->cv_work.notify_one();
+    return BC_OK;
+}
+
+extern "C" bc_status bc_server_poll(bc_server *s, uint64_t ticket, int block, bc_u128 *out, bc_query_stats *st)
+{
+    if (!s) return BC_E_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return BC_E_NOT_FOUND;
+    if (!it->second.done) {
+        if (!block) return BC_E_PENDING;
+        s->cv_done.wait(lk, [&] {
+            auto jt = s->tickets.find(ticket);
+            return jt == s->tickets.end() || jt->second.done;
+        });
+        it = s->tickets.find(ticket);
+        if (it == s->tickets.end()) return BC_E_NOT_FOUND;
+    }
+    const Ticket t = it->second;
+    s->tickets.erase(it);
+    if (st) {
+        st->queue_ms = t.t_start > t.t_submit ? (double)(t.t_start - t.t_submit) / 1e6 : 0.0;
+        st->run_ms = t.t_done > t.t_start && t.t_start ? (double)(t.t_done - t.t_start) / 1e6 : 0.0;
+        st->total_ms = (double)(t.t_done - t.t_submit) / 1e6;
+        st->batch_id = t.batch_id;
+        st->batch_size = t.batch_size;
+        st->pad = 0;
+    }
+    if (t.status == BC_OK && out) *out = t.value;
+    return t.status;
+}
+
+extern "C" bc_status bc_server_stats(bc_server *s, bc_server_summary *out)
+{
+    if (!s || !out) return BC_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->rejected = s->rejected;
+    out->timed_out = s->timed_out;
+    out->failed = s->failed;
+    out->batches = s->batches;
+    out->max_overlap = s->max_overlap;
+    out->mean_batch = s->batches ? (double)s->batched_queries / (double)s->batches : 0.0;
+    if (!s->latencies_ms.empty()) {
+        std::vector<double> v = s->latencies_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double f) {
+            size_t i = (size_t)std::min<double>((double)v.size() - 1, f * (double)(v.size() - 1) + 0.5);
+            return v[i];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_ms = sum / (double)v.size();
+    }
+    const double secs = (double)(bcint::steady_ns() - s->t_created) / 1e9;
+    out->qps = secs > 0 ? (double)s->completed / secs : 0.0;
+    return BC_OK;
+}
+
+extern "C" uint64_t bc_server_now_ns(void) { return bcint::steady_ns(); }
+
+extern "C" void bc_server_destroy(bc_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        const uint64_t now = bcint::steady_ns();
+        for (uint64_t id : s->pending) finish(s, s->tickets[id], BC_E_CANCELLED, bc_u128{0, 0}, now);
+        s->pending.clear();
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+    for (auto &w : s->workers) w.join();
+    delete s;
+}

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bc.h")
+HEADERS = [os.path.join(ROOT, "include", "bc.h"), os.path.join(ROOT, "include", "bc_server.h")]
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +21,7 @@ def bc():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(bc_[a-z0-9_]+)\s*\(", text)))
 
