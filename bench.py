@@ -75,8 +75,12 @@ def main():
     for p, q in queries:
         c, st = bc.bc_count(G, p, q, with_stats=True, instrument=True, stream=stream)
         algo[(p, q)] = (c, st)
+        cyc = {k: st[k] for k in ("cyc_setup", "cyc_compact", "cyc_pair", "cyc_filter")}
+        tot = sum(cyc.values()) or 1
         log(f"[bench] ({p},{q}) count={c} anchor={st['anchor']} tasks={st['tasks']} "
-            f"pair_words={st['pair_ops']} filter_words={st['filter_ops']} ms_enum={st['ms_enumerate']:.1f}")
+            f"pair_words={st['pair_ops']} filter_words={st['filter_ops']} ms_enum={st['ms_enumerate']:.1f} "
+            f"ms_cand={st['ms_candidates']:.1f} ms_rows={st['ms_rows']:.1f} ms_plan={st['ms_plan']:.1f} "
+            f"cycle share " + " ".join(f"{k[4:]}={v / tot:.2f}" for k, v in cyc.items()))
 
     def step():
         out = []

@@ -84,6 +84,8 @@ typedef struct {
     uint64_t row_words;        /* 64-bit words of per-root candidate bitmaps */
     uint64_t pair_ops;         /* instrumented: 64-bit word ANDs+popcounts of the fused leaf pairs */
     uint64_t filter_ops;       /* instrumented: 64-bit word ANDs+popcounts of the child filters */
+    uint64_t cyc_setup, cyc_compact, cyc_pair, cyc_filter;  /* instrumented: shader-clock cycles summed
+                                  over wavefronts in task setup, row compaction, leaf pairs, filters */
 } bc_stats;
 
 /*

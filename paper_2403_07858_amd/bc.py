@@ -58,7 +58,9 @@ class bc_stats(ctypes.Structure):
                 ("ms_rows", ctypes.c_double), ("ms_enumerate", ctypes.c_double), ("anchor", ctypes.c_int32),
                 ("roots", ctypes.c_uint64), ("roots_active", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
                 ("candidate_edges", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
-                ("pair_ops", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64)]
+                ("pair_ops", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64),
+                ("cyc_setup", ctypes.c_uint64), ("cyc_compact", ctypes.c_uint64), ("cyc_pair", ctypes.c_uint64),
+                ("cyc_filter", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

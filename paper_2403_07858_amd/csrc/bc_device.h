@@ -24,7 +24,7 @@ struct Job {
     uint32_t binom_n;       // table length (max degree of A + 1)
     uint32_t n_ovf;         // smallest n with C(n, qA) >= 2^128 (binom_n if none)
     uint32_t slot;          // result slot
-    uint32_t pad;
+    uint32_t n_u64;         // largest n with C(n, qA) < 2^64
     uint64_t deadline;      // device real-time clock tick after which the job gives up (0 = none)
 };
 
@@ -44,6 +44,7 @@ struct Slot {
     unsigned int flags;     // FLAG_* bits
     unsigned int pad;
     unsigned long long pair_ops, filter_ops;
+    unsigned long long cyc_setup, cyc_compact, cyc_pair, cyc_filter;   // instrumented shader-clock sums
 };
 
 enum : unsigned {

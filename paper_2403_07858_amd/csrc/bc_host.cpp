@@ -343,7 +343,7 @@ bc_status device_clock(int device, hipStream_t st, ClockCal &out)
 }
 
 // C(n, q) for n in [0, nmax] as exact u128; n_ovf = first n that overflows.
-void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n_ovf)
+void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n_ovf, uint32_t &n_u64)
 {
     std::vector<u128> c(q + 1, 0);
     std::vector<uint8_t> ov(q + 1, 0);
@@ -361,6 +361,8 @@ void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n
         }
         if (ov[q] && n_ovf > nmax) n_ovf = n;
         col[n] = ov[q] ? 0 : c[q];
+        // C(n, q) does not decrease with n, so the entries below 2^64 are a prefix
+        if (!ov[q] && (c[q] >> 64) == 0) n_u64 = n;
     }
 }
 
@@ -446,7 +448,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     const int device = specs[0].g->device;
     BC_HIP(hipSetDevice(device));
     const uint32_t lds_words = (opts && opts->lds_words) ? opts->lds_words : bcdev::max_lds_words_per_wave();
-    const uint32_t waves_per_cu = (opts && opts->waves_per_cu) ? std::max(4u, opts->waves_per_cu) : 8u;
+    const uint32_t waves_per_cu = (opts && opts->waves_per_cu) ? std::max(4u, opts->waves_per_cu) : 12u;
     const bool instrument = opts && opts->instrument;
     const int ncu = cu_count(device);
     auto t_host0 = std::chrono::steady_clock::now();
@@ -495,8 +497,8 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         const HostJob &hj = jobs[j];
         const bc_graph *g = specs[hj.spec].g;
         const Side &A = g->side[hj.anchor];
-        uint32_t n_ovf = 0;
-        binom_column(A.max_deg, hj.qA, cols[j], n_ovf);
+        uint32_t n_ovf = 0, n_u64 = 0;
+        binom_column(A.max_deg, hj.qA, cols[j], n_ovf, n_u64);
         bcdev::Job &d = hjobs[j];
         memset(&d, 0, sizeof(d));
         d.ptrA = A.d_ptr;
@@ -511,6 +513,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         d.qA = hj.qA;
         d.binom_n = A.max_deg + 1;
         d.n_ovf = n_ovf;
+        d.n_u64 = n_u64;
         d.slot = j;
         d.deadline = 0;
         const uint64_t dl = specs[hj.spec].deadline_ns;
@@ -748,8 +751,13 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         stats->candidate_edges = cand_edges;
         stats->row_words = pool_words;
         for (size_t i = 0; i < ns; ++i) {
-            stats->pair_ops += hs[spec_jobs[i][0]].pair_ops;
-            stats->filter_ops += hs[spec_jobs[i][0]].filter_ops;
+            const bcdev::Slot &sl = hs[spec_jobs[i][0]];
+            stats->pair_ops += sl.pair_ops;
+            stats->filter_ops += sl.filter_ops;
+            stats->cyc_setup += sl.cyc_setup;
+            stats->cyc_compact += sl.cyc_compact;
+            stats->cyc_pair += sl.cyc_pair;
+            stats->cyc_filter += sl.cyc_filter;
         }
     }
     return overall;

@@ -21,7 +21,8 @@
 
 namespace bcdev {
 
-constexpr uint32_t kLdsWordsPerWave = 2048;   // 16 KiB of LDS per wavefront
+constexpr uint32_t kLdsWordsPerWave = 640;    // LDS arena per wavefront (64-bit words)
+constexpr uint32_t kTableLen = 520;           // per-wave LDS copy of C(n, q) for n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
 
 
@@ -185,6 +186,10 @@ __global__ void k_fill_slots(Slot *slots, uint32_t n)
         slots[i].pad = 0;
         slots[i].pair_ops = 0;
         slots[i].filter_ops = 0;
+        slots[i].cyc_setup = 0;
+        slots[i].cyc_compact = 0;
+        slots[i].cyc_pair = 0;
+        slots[i].cyc_filter = 0;
     }
 }
 
@@ -462,11 +467,22 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
 // ---------------------------------------------------------------------------
 // Enumeration.
 
-// Per-lane accumulation of one leaf value C(n, q).
+// Per-lane leaf accumulators.  The u128 total takes the fallback path (table
+// entries of 128 bits read from HBM) and every flush; the hot path adds 64-bit
+// table entries into lo and counts carries in hi.
 struct Acc {
     u128 v;
     bool ovf;
+    uint64_t lo;
+    uint32_t hi;
 };
+
+__device__ __forceinline__ void acc_flush(Acc &a)
+{
+    a.ovf |= __builtin_add_overflow(a.v, ((u128)a.hi << 64) | (u128)a.lo, &a.v);
+    a.lo = 0;
+    a.hi = 0;
+}
 
 __device__ __forceinline__ void leaf_add(Acc &a, const u128 *binom, uint32_t n_ovf, uint32_t n)
 {
@@ -477,33 +493,103 @@ __device__ __forceinline__ void leaf_add(Acc &a, const u128 *binom, uint32_t n_o
     a.ovf |= __builtin_add_overflow(a.v, binom[n], &a.v);
 }
 
-// sum over a < b < m of C(popcount(row_a & row_b), q).  Rows are column-major
-// in blk with the given stride; W words each, W <= WR held in registers.
-template <int WR>
-__device__ void pair_sum_reg(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W,
-                             const u128 *binom, uint32_t q, uint32_t n_ovf, Acc &acc)
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane)
 {
-    const uint32_t ln = lane_id();
-    for (uint32_t b0 = 1; b0 < m; b0 += kWaveSize) {
-        const uint32_t b = b0 + ln;
-        const bool valid = b < m;
-        uint64_t rb[WR];
-#pragma unroll
-        for (int w = 0; w < WR; ++w) rb[w] = (valid && (uint32_t)w < W) ? blk[(uint64_t)w * stride + b] : 0ull;
-        const uint32_t amax = min(m - 1, b0 + kWaveSize - 1);
-        for (uint32_t a = 0; a < amax; ++a) {
-            uint32_t n = 0;
-#pragma unroll
-            for (int w = 0; w < WR; ++w)
-                if ((uint32_t)w < W) n += __popcll(blk[(uint64_t)w * stride + a] & rb[w]);
-            if (valid && a < b && n >= q) leaf_add(acc, binom, n_ovf, n);
-        }
-    }
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, (int)lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)lane);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// Same sum for wide rows, read from memory word by word.
-__device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W,
-                             const u128 *binom, uint32_t q, uint32_t n_ovf, Acc &acc)
+// Per-wave copy of the low 64 bits of C(n, q) for n < len, valid for the job
+// it was loaded for while every entry needed is below 2^64.
+struct Table {
+    uint64_t *t;         // LDS
+    uint32_t job, len;
+};
+
+// Makes tbl hold entries [0, need) of job j; false if they do not all fit
+// (table too short or some entry >= 2^64), in which case the caller uses the
+// u128 table in HBM.
+__device__ bool table_ready(Table &tb, const Job &jb, uint32_t j, uint32_t need)
+{
+    if (need > kTableLen || need > jb.n_u64 + 1 || need > jb.binom_n) return false;
+    if (tb.job == j && tb.len >= need) return true;
+    const uint32_t len = min(kTableLen, min(jb.binom_n, jb.n_u64 + 1));
+    for (uint32_t n = lane_id(); n < len; n += kWaveSize) tb.t[n] = (uint64_t)jb.binom[n];
+    wave_sync();
+    tb.job = j;
+    tb.len = len;
+    return true;
+}
+
+// sum over a < b < m of C(popcount(row_a & row_b), q), rows column-major in
+// blk (stride), W <= WR words.  64-row tiles of a are loaded coalesced and
+// broadcast row by row with readlane; each lane owns one b; the leaf value
+// comes from the wave's LDS table.
+// Adds tbl[n] into the 64-bit leaf accumulator with carry counting.
+__device__ __forceinline__ void acc_add64(Acc &acc, uint64_t x)
+{
+    acc.lo += x;
+    acc.hi += (acc.lo < x) ? 1u : 0u;
+}
+
+template <int WR>
+__device__ __forceinline__ uint32_t and_popcount(const uint64_t (&ta)[WR], uint32_t j, const uint64_t (&rb)[WR],
+                                                 uint32_t W)
+{
+    uint32_t n = 0;
+#pragma unroll
+    for (int w = 0; w < WR; ++w)
+        if ((uint32_t)w < W) n += __popcll(readlane64(ta[w], j) & rb[w]);
+    return n;
+}
+
+// sum over a < b < m of C(popcount(row_a & row_b), q), rows column-major in
+// blk (stride), W <= WR words.  64-row tiles of a are loaded coalesced and
+// broadcast row by row with readlane; each lane owns one b; the leaf value
+// comes from the wave's LDS table.  Lanes past m hold zero rows, so they add
+// C(0, q) = 0 and need no mask; only the diagonal tile masks a >= b.
+template <int WR>
+__device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const uint64_t *tbl,
+                              Acc &acc)
+{
+    const uint32_t ln = lane_id();
+    for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize) {
+        const uint32_t b = b0 + ln;
+        const bool bv = b < m;
+        uint64_t rb[WR];
+#pragma unroll
+        for (int w = 0; w < WR; ++w) rb[w] = (bv && (uint32_t)w < W) ? blk[(uint64_t)w * stride + b] : 0ull;
+        for (uint32_t a0 = 0; a0 < b0; a0 += kWaveSize) {
+            uint64_t ta[WR];
+#pragma unroll
+            for (int w = 0; w < WR; ++w) ta[w] = ((uint32_t)w < W) ? blk[(uint64_t)w * stride + a0 + ln] : 0ull;
+            for (uint32_t j = 0; j < (uint32_t)kWaveSize; j += 4) {
+                const uint32_t n0 = and_popcount<WR>(ta, j, rb, W);
+                const uint32_t n1 = and_popcount<WR>(ta, j + 1, rb, W);
+                const uint32_t n2 = and_popcount<WR>(ta, j + 2, rb, W);
+                const uint32_t n3 = and_popcount<WR>(ta, j + 3, rb, W);
+                const uint64_t x0 = tbl[n0], x1 = tbl[n1], x2 = tbl[n2], x3 = tbl[n3];
+                acc_add64(acc, x0);
+                acc_add64(acc, x1);
+                acc_add64(acc, x2);
+                acc_add64(acc, x3);
+            }
+        }
+        // diagonal tile: a = b0 + j pairs with lanes ln > j
+        const uint32_t jn = min((uint32_t)kWaveSize, m - b0) - 1;
+        for (uint32_t j = 0; j < jn; ++j) {
+            const uint32_t n = and_popcount<WR>(rb, j, rb, W);
+            const uint64_t x = (j < ln) ? tbl[n] : 0ull;
+            acc_add64(acc, x);
+        }
+    }
+    acc_flush(acc);
+}
+
+// Same sum through the u128 table in HBM (wide rows or entries >= 2^64).
+__device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const u128 *binom,
+                             uint32_t q, uint32_t n_ovf, Acc &acc)
 {
     const uint32_t ln = lane_id();
     for (uint32_t b0 = 1; b0 < m; b0 += kWaveSize) {
@@ -520,15 +606,19 @@ __device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, u
     }
 }
 
-__device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const u128 *binom,
-                         uint32_t q, uint32_t n_ovf, Acc &acc)
+__device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, uint32_t nbits,
+                         const Job &jb, uint32_t j, Table &tb, Acc &acc)
 {
     if (m < 2) return;
-    if (W <= 1) pair_sum_reg<1>(blk, stride, m, W, binom, q, n_ovf, acc);
-    else if (W <= 2) pair_sum_reg<2>(blk, stride, m, W, binom, q, n_ovf, acc);
-    else if (W <= 4) pair_sum_reg<4>(blk, stride, m, W, binom, q, n_ovf, acc);
-    else if (W <= 8) pair_sum_reg<8>(blk, stride, m, W, binom, q, n_ovf, acc);
-    else pair_sum_mem(blk, stride, m, W, binom, q, n_ovf, acc);
+    // every popcount is at most nbits (the compacted universe)
+    if (W <= 8 && table_ready(tb, jb, j, nbits + 1)) {
+        if (W <= 1) pair_sum_tile<1>(blk, stride, m, W, tb.t, acc);
+        else if (W <= 2) pair_sum_tile<2>(blk, stride, m, W, tb.t, acc);
+        else if (W <= 4) pair_sum_tile<4>(blk, stride, m, W, tb.t, acc);
+        else pair_sum_tile<8>(blk, stride, m, W, tb.t, acc);
+    } else {
+        pair_sum_mem(blk, stride, m, W, jb.binom, jb.qA, jb.n_ovf, acc);
+    }
 }
 
 // Children of row a: rows b > a whose AND with row a keeps >= q bits, written
@@ -582,10 +672,18 @@ __device__ __forceinline__ uint64_t *arena_alloc(Arena &ar, uint64_t words, bool
     return nullptr;
 }
 
+// Work and cycle counters of one wavefront (uniform values).
+struct Counters {
+    unsigned long long pair_words, filter_words;
+    unsigned long long cyc_setup, cyc_compact, cyc_pair, cyc_filter;
+};
+
+__device__ __forceinline__ uint64_t cycles() { return __builtin_amdgcn_s_memtime(); }
+
 // One (root, second vertex) task: the node {u, c_i} of the search tree.
-__device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const uint64_t *pool, Arena ar,
-                         uint64_t *stack, Acc &acc, unsigned long long &pair_ops,
-                         unsigned long long &filter_ops, bool *cap_fail, bool *timed_out)
+__device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, const uint64_t *pool,
+                         Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument,
+                         bool *cap_fail, bool *timed_out)
 {
     const uint32_t ln = lane_id();
     const uint32_t u = rt.root;
@@ -594,6 +692,7 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
     const uint32_t k = rt.k;
     const uint64_t *base = pool + rt.pool_off;
     const uint32_t q = jb.qA, pA = jb.pA;
+    uint64_t t0 = instrument ? cycles() : 0;
 
     // S2 = row i (common neighbours of u and c_i) and its word prefix counts.
     uint64_t *s2 = arena_alloc(ar, 2ull * W1, cap_fail);
@@ -613,7 +712,12 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
     const uint32_t s2n = running;
     const uint32_t W2 = (s2n + 63) >> 6;
     const uint32_t rem = k - i - 1;
-    filter_ops += (unsigned long long)rem * W1;
+    ct.filter_words += (unsigned long long)rem * W1;
+    if (instrument) {
+        const uint64_t t1 = cycles();
+        ct.cyc_setup += t1 - t0;
+        t0 = t1;
+    }
 
     if (pA == 3) {
         // Leaves {u, c_i, c_b}: sum of C(|S2 n row_b|, q).
@@ -625,6 +729,7 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
                 if (n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
             }
         }
+        if (instrument) ct.cyc_compact += cycles() - t0;
         return;
     }
 
@@ -670,16 +775,22 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
         m2 += (uint32_t)__popcll(mask);
     }
     wave_sync();
+    if (instrument) {
+        const uint64_t t1 = cycles();
+        ct.cyc_compact += t1 - t0;
+        t0 = t1;
+    }
     if (m2 < pA - 2) return;
     if (pA == 4) {
-        pair_sum(blk2, rem, m2, W2, jb.binom, q, jb.n_ovf, acc);
-        pair_ops += (unsigned long long)m2 * (m2 - 1) / 2 * W2;
+        pair_sum(blk2, rem, m2, W2, s2n, jb, jidx, tb, acc);
+        ct.pair_words += (unsigned long long)m2 * (m2 - 1) / 2 * W2;
+        if (instrument) ct.cyc_pair += cycles() - t0;
         return;
     }
 
     // DFS over levels 2 .. pA-3; the node at level pA-2 is finished by pair_sum.
     // stack[4*d + 0] = block offset (bit 63: in slab), [1] = stride | m << 32,
-    // [2] = cursor, [3] = arena marks (lds_used | slab_used << 32 when small).
+    // [2] = cursor, [3] = arena marks (lds_used | slab_used << 32).
     auto enc_ptr = [&](const uint64_t *p) -> uint64_t {
         return (p >= ar.lds && p < ar.lds + ar.lds_cap) ? (uint64_t)(p - ar.lds)
                                                         : ((uint64_t)(p - ar.slab) | (1ull << 63));
@@ -716,12 +827,19 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
         const uint64_t mark = (uint64_t)ar.lds_used | (ar.slab_used << 32);
         uint64_t *nb = arena_alloc(ar, (uint64_t)cap * W2, cap_fail);
         if (!nb) return;
+        if (instrument) t0 = cycles();
         const uint32_t mc = filter_children(blk, stride, m, a, W2, q, nb, cap);
-        filter_ops += (unsigned long long)cap * W2;
+        ct.filter_words += (unsigned long long)cap * W2;
+        if (instrument) {
+            const uint64_t t1 = cycles();
+            ct.cyc_filter += t1 - t0;
+            t0 = t1;
+        }
         if (mc >= pA - d - 1) {
             if (d + 1 == pA - 2) {
-                pair_sum(nb, cap, mc, W2, jb.binom, q, jb.n_ovf, acc);
-                pair_ops += (unsigned long long)mc * (mc - 1) / 2 * W2;
+                pair_sum(nb, cap, mc, W2, s2n, jb, jidx, tb, acc);
+                ct.pair_words += (unsigned long long)mc * (mc - 1) / 2 * W2;
+                if (instrument) ct.cyc_pair += cycles() - t0;
             } else {
                 ++d;
                 stack[4 * d + 0] = enc_ptr(nb);
@@ -736,9 +854,25 @@ __device__ void run_task(const Job &jb, const ActiveRoot &rt, uint32_t i, const 
     }
 }
 
+__device__ void enum_flush(Slot *slots, uint32_t slot, Acc &acc, Counters &ct, bool instrument)
+{
+    acc_flush(acc);
+    wave_flush(slots, slot, acc.v, acc.ovf, ct.pair_words, ct.filter_words);
+    if (instrument && lane_id() == 0) {
+        atomicAdd(&slots[slot].cyc_setup, ct.cyc_setup);
+        atomicAdd(&slots[slot].cyc_compact, ct.cyc_compact);
+        atomicAdd(&slots[slot].cyc_pair, ct.cyc_pair);
+        atomicAdd(&slots[slot].cyc_filter, ct.cyc_filter);
+    }
+    acc.v = 0;
+    acc.ovf = false;
+    ct = Counters{};
+}
+
 __global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
 {
     __shared__ uint64_t lds[kWavesPerBlock][kLdsWordsPerWave];
+    __shared__ uint64_t tbl[kWavesPerBlock][kTableLen];
     const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
     const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     uint64_t *stack = &lds[wv][0];
@@ -749,11 +883,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
     arena.slab = prm.slab + wave_global * prm.slab_words;
     arena.slab_cap = prm.slab_words;
     arena.slab_used = 0;
+    Table tb;
+    tb.t = &tbl[wv][0];
+    tb.job = 0xffffffffu;
+    tb.len = 0;
+    const bool instrument = prm.instrument != 0;
 
     Acc acc;
     acc.v = 0;
     acc.ovf = false;
-    unsigned long long pair_ops = 0, filter_ops = 0;
+    acc.lo = 0;
+    acc.hi = 0;
+    Counters ct{};
     uint32_t cur_job = 0xffffffffu;
     for (;;) {
         unsigned long long t = 0;
@@ -769,25 +910,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
         }
         const ActiveRoot rt = prm.roots[lo];
         if (rt.job != cur_job) {
-            if (cur_job != 0xffffffffu)
-                wave_flush(prm.slots, prm.jobs[cur_job].slot, acc.v, acc.ovf, pair_ops, filter_ops);
-            acc.v = 0;
-            acc.ovf = false;
-            pair_ops = 0;
-            filter_ops = 0;
+            if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
             cur_job = rt.job;
         }
         const Job jb = prm.jobs[rt.job];
         bool cap_fail = false, timed_out = past_deadline(jb.deadline);
         if (!timed_out)
-            run_task(jb, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, acc, pair_ops, filter_ops,
+            run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct, instrument,
                      &cap_fail, &timed_out);
         if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
         if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
     }
-    if (cur_job != 0xffffffffu)
-        wave_flush(prm.slots, prm.jobs[cur_job].slot, acc.v, acc.ovf, prm.instrument ? pair_ops : 0,
-                   prm.instrument ? filter_ops : 0);
+    if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
 }
 
 hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream)

@@ -101,12 +101,12 @@ def test_deadline_and_admission(bc, graphs):
 
 
 def test_device_time_limit(bc):
-    # a dense graph whose (6,6) count runs far longer than 50 ms
-    g = gg.chung_lu_bipartite(3000, 1500, 60000, 2.1, 2.1, 600, 600, seed=21)
+    # (5,5) on the power-law 2M-edge graph runs for seconds; 20 ms must stop it
+    g = gg.power_law_2m()
     G = bc.build_graph(g)
     t0 = time.time()
     with pytest.raises(bc.BCError) as e:
-        bc.bc_count(G, 6, 6, timeout_ms=50)
+        bc.bc_count(G, 5, 5, timeout_ms=20)
     assert e.value.status == bc.BC_E_TIMEOUT
     assert time.time() - t0 < 30
     # the library keeps working afterwards
