@@ -21,7 +21,7 @@
 
 namespace bcdev {
 
-constexpr uint32_t kLdsWordsPerWave = 640;    // LDS arena per wavefront (64-bit words)
+constexpr uint32_t kLdsWordsPerWave = 600;    // LDS arena per wavefront (64-bit words)
 constexpr uint32_t kTableLen = 520;           // per-wave LDS copy of C(n, q) for n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
 
@@ -473,15 +473,13 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
 struct Acc {
     u128 v;
     bool ovf;
-    uint64_t lo;
-    uint32_t hi;
+    u128 t;   // 64-bit leaf values of the current task: fewer than 2^64 of them, so t cannot wrap
 };
 
 __device__ __forceinline__ void acc_flush(Acc &a)
 {
-    a.ovf |= __builtin_add_overflow(a.v, ((u128)a.hi << 64) | (u128)a.lo, &a.v);
-    a.lo = 0;
-    a.hi = 0;
+    a.ovf |= __builtin_add_overflow(a.v, a.t, &a.v);
+    a.t = 0;
 }
 
 __device__ __forceinline__ void leaf_add(Acc &a, const u128 *binom, uint32_t n_ovf, uint32_t n)
@@ -504,6 +502,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane)
 // it was loaded for while every entry needed is below 2^64.
 struct Table {
     uint64_t *t;         // LDS
+    uint64_t *tile;      // LDS staging of one 64-row tile (64 x 8 words)
     uint32_t job, len;
 };
 
@@ -526,63 +525,59 @@ __device__ bool table_ready(Table &tb, const Job &jb, uint32_t j, uint32_t need)
 // blk (stride), W <= WR words.  64-row tiles of a are loaded coalesced and
 // broadcast row by row with readlane; each lane owns one b; the leaf value
 // comes from the wave's LDS table.
-// Adds tbl[n] into the 64-bit leaf accumulator with carry counting.
-__device__ __forceinline__ void acc_add64(Acc &acc, uint64_t x)
-{
-    acc.lo += x;
-    acc.hi += (acc.lo < x) ? 1u : 0u;
-}
-
-template <int WR>
-__device__ __forceinline__ uint32_t and_popcount(const uint64_t (&ta)[WR], uint32_t j, const uint64_t (&rb)[WR],
-                                                 uint32_t W)
+template <int W>
+__device__ __forceinline__ uint32_t and_popcount(const uint64_t *row, const uint64_t (&rb)[W])
 {
     uint32_t n = 0;
 #pragma unroll
-    for (int w = 0; w < WR; ++w)
-        if ((uint32_t)w < W) n += __popcll(readlane64(ta[w], j) & rb[w]);
+    for (int w = 0; w < W; ++w) n += __popcll(row[w] & rb[w]);
     return n;
 }
 
-// sum over a < b < m of C(popcount(row_a & row_b), q), rows column-major in
-// blk (stride), W <= WR words.  64-row tiles of a are loaded coalesced and
-// broadcast row by row with readlane; each lane owns one b; the leaf value
-// comes from the wave's LDS table.  Lanes past m hold zero rows, so they add
+// sum over a < b < m of C(popcount(row_a & row_b), q), rows of exactly W
+// words column-major in blk (stride).  Each lane owns one b; 64-row tiles of
+// a are loaded coalesced, staged row-major in the wave's LDS tile and read
+// back row by row with one broadcast LDS read per word; the leaf value comes
+// from the wave's LDS table.  Lanes past m hold zero rows, so they add
 // C(0, q) = 0 and need no mask; only the diagonal tile masks a >= b.
-template <int WR>
-__device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const uint64_t *tbl,
-                              Acc &acc)
+template <int W>
+__device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, const uint64_t *tbl,
+                              uint64_t *tile, Acc &acc)
 {
     const uint32_t ln = lane_id();
     for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize) {
         const uint32_t b = b0 + ln;
         const bool bv = b < m;
-        uint64_t rb[WR];
+        uint64_t rb[W];
 #pragma unroll
-        for (int w = 0; w < WR; ++w) rb[w] = (bv && (uint32_t)w < W) ? blk[(uint64_t)w * stride + b] : 0ull;
+        for (int w = 0; w < W; ++w) rb[w] = bv ? blk[(uint64_t)w * stride + b] : 0ull;
         for (uint32_t a0 = 0; a0 < b0; a0 += kWaveSize) {
-            uint64_t ta[WR];
 #pragma unroll
-            for (int w = 0; w < WR; ++w) ta[w] = ((uint32_t)w < W) ? blk[(uint64_t)w * stride + a0 + ln] : 0ull;
+            for (int w = 0; w < W; ++w) tile[ln * W + w] = blk[(uint64_t)w * stride + a0 + ln];
+            wave_sync();
             for (uint32_t j = 0; j < (uint32_t)kWaveSize; j += 4) {
-                const uint32_t n0 = and_popcount<WR>(ta, j, rb, W);
-                const uint32_t n1 = and_popcount<WR>(ta, j + 1, rb, W);
-                const uint32_t n2 = and_popcount<WR>(ta, j + 2, rb, W);
-                const uint32_t n3 = and_popcount<WR>(ta, j + 3, rb, W);
+                const uint32_t n0 = and_popcount<W>(tile + (j + 0) * W, rb);
+                const uint32_t n1 = and_popcount<W>(tile + (j + 1) * W, rb);
+                const uint32_t n2 = and_popcount<W>(tile + (j + 2) * W, rb);
+                const uint32_t n3 = and_popcount<W>(tile + (j + 3) * W, rb);
                 const uint64_t x0 = tbl[n0], x1 = tbl[n1], x2 = tbl[n2], x3 = tbl[n3];
-                acc_add64(acc, x0);
-                acc_add64(acc, x1);
-                acc_add64(acc, x2);
-                acc_add64(acc, x3);
+                acc.t += x0;
+                acc.t += x1;
+                acc.t += x2;
+                acc.t += x3;
             }
+            wave_sync();
         }
         // diagonal tile: a = b0 + j pairs with lanes ln > j
+#pragma unroll
+        for (int w = 0; w < W; ++w) tile[ln * W + w] = rb[w];
+        wave_sync();
         const uint32_t jn = min((uint32_t)kWaveSize, m - b0) - 1;
         for (uint32_t j = 0; j < jn; ++j) {
-            const uint32_t n = and_popcount<WR>(rb, j, rb, W);
-            const uint64_t x = (j < ln) ? tbl[n] : 0ull;
-            acc_add64(acc, x);
+            const uint32_t n = and_popcount<W>(tile + j * W, rb);
+            acc.t += (j < ln) ? tbl[n] : 0ull;
         }
+        wave_sync();
     }
     acc_flush(acc);
 }
@@ -612,10 +607,16 @@ __device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint3
     if (m < 2) return;
     // every popcount is at most nbits (the compacted universe)
     if (W <= 8 && table_ready(tb, jb, j, nbits + 1)) {
-        if (W <= 1) pair_sum_tile<1>(blk, stride, m, W, tb.t, acc);
-        else if (W <= 2) pair_sum_tile<2>(blk, stride, m, W, tb.t, acc);
-        else if (W <= 4) pair_sum_tile<4>(blk, stride, m, W, tb.t, acc);
-        else pair_sum_tile<8>(blk, stride, m, W, tb.t, acc);
+        switch (W) {
+        case 1: pair_sum_tile<1>(blk, stride, m, tb.t, tb.tile, acc); break;
+        case 2: pair_sum_tile<2>(blk, stride, m, tb.t, tb.tile, acc); break;
+        case 3: pair_sum_tile<3>(blk, stride, m, tb.t, tb.tile, acc); break;
+        case 4: pair_sum_tile<4>(blk, stride, m, tb.t, tb.tile, acc); break;
+        case 5: pair_sum_tile<5>(blk, stride, m, tb.t, tb.tile, acc); break;
+        case 6: pair_sum_tile<6>(blk, stride, m, tb.t, tb.tile, acc); break;
+        case 7: pair_sum_tile<7>(blk, stride, m, tb.t, tb.tile, acc); break;
+        default: pair_sum_tile<8>(blk, stride, m, tb.t, tb.tile, acc); break;
+        }
     } else {
         pair_sum_mem(blk, stride, m, W, jb.binom, jb.qA, jb.n_ovf, acc);
     }
@@ -712,12 +713,46 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     const uint32_t s2n = running;
     const uint32_t W2 = (s2n + 63) >> 6;
     const uint32_t rem = k - i - 1;
-    ct.filter_words += (unsigned long long)rem * W1;
     if (instrument) {
         const uint64_t t1 = cycles();
         ct.cyc_setup += t1 - t0;
         t0 = t1;
     }
+
+    // The nonzero words of S2, each with the six masks of the compress
+    // operation (Hacker's Delight, "compress" / parallel bit extract) that
+    // packs the bits selected by that word to the right: entry e holds
+    // {s2 word, mv0..mv5, w | pre << 32}.  Empty words of S2 are skipped.
+    uint64_t *nzt = arena_alloc(ar, 8ull * W1, cap_fail);
+    if (!nzt) return;
+    uint32_t nz = 0;
+    for (uint32_t w0 = 0; w0 < W1; w0 += kWaveSize) {
+        const uint32_t w = w0 + ln;
+        const uint64_t sw = (w < W1) ? s2[w] : 0ull;
+        const uint64_t nzmask = __ballot(sw != 0);
+        if (sw != 0) {
+            uint64_t *e = nzt + 8ull * (nz + mbcnt64(nzmask));
+            e[0] = sw;
+            uint64_t m = sw, mk = ~sw << 1;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                uint64_t mp = mk ^ (mk << 1);
+                mp ^= mp << 2;
+                mp ^= mp << 4;
+                mp ^= mp << 8;
+                mp ^= mp << 16;
+                mp ^= mp << 32;
+                const uint64_t mv = mp & m;
+                e[1 + r] = mv;
+                m = (m ^ mv) | (mv >> (1 << r));
+                mk &= ~mp;
+            }
+            e[7] = (uint64_t)w | ((uint64_t)pre[w] << 32);
+        }
+        nz += (uint32_t)__popcll(nzmask);
+    }
+    wave_sync();
+    ct.filter_words += (unsigned long long)rem * nz;
 
     if (pA == 3) {
         // Leaves {u, c_i, c_b}: sum of C(|S2 n row_b|, q).
@@ -725,7 +760,10 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
             const uint32_t b = b0 + ln;
             if (b < k) {
                 uint32_t n = 0;
-                for (uint32_t w = 0; w < W1; ++w) n += __popcll(s2[w] & base[(uint64_t)w * k + b]);
+                for (uint32_t e = 0; e < nz; ++e) {
+                    const uint32_t w = (uint32_t)nzt[8ull * e + 7];
+                    n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + b]);
+                }
                 if (n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
             }
         }
@@ -740,34 +778,47 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
         const uint32_t b = b0 + ln;
         const bool valid = b < k;
+        const uint32_t bb = valid ? b : i;
         uint32_t n = 0;
-        if (valid)
-            for (uint32_t w = 0; w < W1; ++w) n += __popcll(s2[w] & base[(uint64_t)w * k + b]);
+        for (uint32_t e = 0; e < nz; ++e) {
+            const uint32_t w = (uint32_t)nzt[8ull * e + 7];
+            n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + bb]);
+        }
         const bool keep = valid && n >= q;
         const uint64_t mask = __ballot(keep);
-        if (keep) {
+        if (mask) {
+            // every lane walks the same entries (uniform control flow); lanes
+            // that do not keep their row write nothing
             const uint32_t idx = m2 + mbcnt64(mask);
             uint32_t ow = 0;
             uint64_t cur = 0;
-            for (uint32_t w = 0; w < W1; ++w) {
-                const uint64_t sw = s2[w];
-                uint64_t bits = sw & base[(uint64_t)w * k + b];
-                const uint32_t p0 = (uint32_t)pre[w];
-                while (bits) {
-                    const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    const uint32_t pos = p0 + (uint32_t)__popcll(sw & ((1ull << bt) - 1ull));
-                    const uint32_t tw = pos >> 6;
-                    while (ow < tw) {
-                        blk2[(uint64_t)ow * rem + idx] = cur;
-                        cur = 0;
-                        ++ow;
-                    }
-                    cur |= 1ull << (pos & 63);
+            for (uint32_t e = 0; e < nz; ++e) {
+                const uint64_t *en = nzt + 8ull * e;
+                const uint64_t sw = en[0];
+                const uint32_t w = (uint32_t)en[7];
+                const uint32_t o = (uint32_t)(en[7] >> 32);   // first output bit of this word
+                uint64_t x = sw & base[(uint64_t)w * k + bb];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    const uint64_t t = x & en[1 + r];
+                    x = (x ^ t) | (t >> (1 << r));
+                }
+                const uint32_t cnt = (uint32_t)__popcll(sw);
+                const uint32_t tw = o >> 6, sh = o & 63;
+                while (ow < tw) {
+                    if (keep) blk2[(uint64_t)ow * rem + idx] = cur;
+                    cur = 0;
+                    ++ow;
+                }
+                cur |= x << sh;
+                if (sh + cnt > 64) {
+                    if (keep) blk2[(uint64_t)ow * rem + idx] = cur;
+                    cur = x >> (64 - sh);
+                    ++ow;
                 }
             }
             while (ow < W2) {
-                blk2[(uint64_t)ow * rem + idx] = cur;
+                if (keep) blk2[(uint64_t)ow * rem + idx] = cur;
                 cur = 0;
                 ++ow;
             }
@@ -869,10 +920,13 @@ __device__ void enum_flush(Slot *slots, uint32_t slot, Acc &acc, Counters &ct, b
     ct = Counters{};
 }
 
-__global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
+// Three waves per SIMD (12 per CU): the register budget is capped at 168 VGPRs.
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_enumerate(
+    EnumParams prm)
 {
     __shared__ uint64_t lds[kWavesPerBlock][kLdsWordsPerWave];
     __shared__ uint64_t tbl[kWavesPerBlock][kTableLen];
+    __shared__ uint64_t tiles[kWavesPerBlock][kWaveSize * 8];
     const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
     const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     uint64_t *stack = &lds[wv][0];
@@ -885,6 +939,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
     arena.slab_used = 0;
     Table tb;
     tb.t = &tbl[wv][0];
+    tb.tile = &tiles[wv][0];
     tb.job = 0xffffffffu;
     tb.len = 0;
     const bool instrument = prm.instrument != 0;
@@ -892,8 +947,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enumerate(EnumParams prm)
     Acc acc;
     acc.v = 0;
     acc.ovf = false;
-    acc.lo = 0;
-    acc.hi = 0;
+    acc.t = 0;
     Counters ct{};
     uint32_t cur_job = 0xffffffffu;
     for (;;) {
