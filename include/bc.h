@@ -86,6 +86,8 @@ typedef struct {
     uint64_t filter_ops;       /* instrumented: 64-bit word ANDs+popcounts of the child filters */
     uint64_t cyc_setup, cyc_compact, cyc_pair, cyc_filter;  /* instrumented: shader-clock cycles summed
                                   over wavefronts in task setup, row compaction, leaf pairs, filters */
+    uint64_t pairs;            /* instrumented: leaf pairs evaluated */
+    uint64_t pair_slots;       /* instrumented: lane-slots spent on them (pairs / pair_slots = lane use) */
 } bc_stats;
 
 /*

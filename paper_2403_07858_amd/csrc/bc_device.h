@@ -26,6 +26,8 @@ struct Job {
     uint32_t slot;          // result slot
     uint32_t n_u64;         // largest n with C(n, qA) < 2^64
     uint64_t deadline;      // device real-time clock tick after which the job gives up (0 = none)
+    uint32_t n_u58;         // largest n with C(n, qA) < 2^58 (64 such values add up in 64 bits)
+    uint32_t pad2;
 };
 
 // One root that owns enumeration tasks, in schedule (cost) order.
@@ -45,6 +47,7 @@ struct Slot {
     unsigned int pad;
     unsigned long long pair_ops, filter_ops;
     unsigned long long cyc_setup, cyc_compact, cyc_pair, cyc_filter;   // instrumented shader-clock sums
+    unsigned long long pairs, pair_slots;   // instrumented: leaf pairs, and lane-slots spent on them
 };
 
 enum : unsigned {

@@ -22,7 +22,8 @@
 namespace bcdev {
 
 constexpr uint32_t kLdsWordsPerWave = 600;    // LDS arena per wavefront (64-bit words)
-constexpr uint32_t kTableLen = 520;           // per-wave LDS copy of C(n, q) for n < kTableLen
+constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of the tiled leaf sum
+constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
 
 
@@ -190,6 +191,8 @@ __global__ void k_fill_slots(Slot *slots, uint32_t n)
         slots[i].cyc_compact = 0;
         slots[i].cyc_pair = 0;
         slots[i].cyc_filter = 0;
+        slots[i].pairs = 0;
+        slots[i].pair_slots = 0;
     }
 }
 
@@ -502,7 +505,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane)
 // it was loaded for while every entry needed is below 2^64.
 struct Table {
     uint64_t *t;         // LDS
-    uint64_t *tile;      // LDS staging of one 64-row tile (64 x 8 words)
+    uint64_t *tile;      // LDS staging of one 64-row tile (64 x kTileWords words)
     uint32_t job, len;
 };
 
@@ -539,8 +542,17 @@ __device__ __forceinline__ uint32_t and_popcount(const uint64_t *row, const uint
 // a are loaded coalesced, staged row-major in the wave's LDS tile and read
 // back row by row with one broadcast LDS read per word; the leaf value comes
 // from the wave's LDS table.  Lanes past m hold zero rows, so they add
-// C(0, q) = 0 and need no mask; only the diagonal tile masks a >= b.
-template <int W>
+// C(0, q) = 0 and need no mask.
+//
+// The diagonal tile (the t <= 64 rows b0 .. b0+t-1 paired among themselves)
+// is folded round-robin: in step d = 1, 2, ... lane b pairs with row
+// (b + d) mod t.  Every unordered pair has exactly one difference d <= t/2
+// (both differences equal t/2 when t is even, where only lanes b < t/2
+// count), so floor(t/2) steps with all lanes busy replace t - 1 masked ones.
+//
+// Small: every table entry is below 2^58, so 64 of them add up in 64 bits;
+// the tile sums go into the 128-bit task sum once per tile.
+template <int W, bool Small>
 __device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, const uint64_t *tbl,
                               uint64_t *tile, Acc &acc)
 {
@@ -555,28 +567,40 @@ __device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, 
 #pragma unroll
             for (int w = 0; w < W; ++w) tile[ln * W + w] = blk[(uint64_t)w * stride + a0 + ln];
             wave_sync();
-            for (uint32_t j = 0; j < (uint32_t)kWaveSize; j += 4) {
-                const uint32_t n0 = and_popcount<W>(tile + (j + 0) * W, rb);
-                const uint32_t n1 = and_popcount<W>(tile + (j + 1) * W, rb);
-                const uint32_t n2 = and_popcount<W>(tile + (j + 2) * W, rb);
-                const uint32_t n3 = and_popcount<W>(tile + (j + 3) * W, rb);
-                const uint64_t x0 = tbl[n0], x1 = tbl[n1], x2 = tbl[n2], x3 = tbl[n3];
-                acc.t += x0;
-                acc.t += x1;
-                acc.t += x2;
-                acc.t += x3;
+            uint64_t s = 0;
+            for (uint32_t j = 0; j < (uint32_t)kWaveSize; j += 8) {
+                uint32_t n[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) n[r] = and_popcount<W>(tile + (j + r) * W, rb);
+                uint64_t x[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) x[r] = tbl[n[r]];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    if (Small) s += x[r];
+                    else acc.t += x[r];
+                }
             }
+            if (Small) acc.t += s;
             wave_sync();
         }
-        // diagonal tile: a = b0 + j pairs with lanes ln > j
+        // diagonal tile, folded round-robin
+        const uint32_t t = min((uint32_t)kWaveSize, m - b0);
 #pragma unroll
         for (int w = 0; w < W; ++w) tile[ln * W + w] = rb[w];
         wave_sync();
-        const uint32_t jn = min((uint32_t)kWaveSize, m - b0) - 1;
-        for (uint32_t j = 0; j < jn; ++j) {
-            const uint32_t n = and_popcount<W>(tile + j * W, rb);
-            acc.t += (j < ln) ? tbl[n] : 0ull;
+        const uint32_t half = t >> 1;
+        uint64_t s = 0;
+        uint32_t a = ln;
+        for (uint32_t d = 1; d <= half; ++d) {
+            a = (a + 1 == t) ? 0u : a + 1;                    // (ln + d) mod t for lanes ln < t
+            const uint32_t n = and_popcount<W>(tile + (ln < t ? a : 0u) * W, rb);
+            const bool take = (2 * d != t) || (ln < half);    // d = t/2: each pair once
+            const uint64_t x = take ? tbl[n] : 0ull;
+            if (Small) s += x;
+            else acc.t += x;
         }
+        if (Small) acc.t += s;
         wave_sync();
     }
     acc_flush(acc);
@@ -606,16 +630,21 @@ __device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint3
 {
     if (m < 2) return;
     // every popcount is at most nbits (the compacted universe)
-    if (W <= 8 && table_ready(tb, jb, j, nbits + 1)) {
-        switch (W) {
-        case 1: pair_sum_tile<1>(blk, stride, m, tb.t, tb.tile, acc); break;
-        case 2: pair_sum_tile<2>(blk, stride, m, tb.t, tb.tile, acc); break;
-        case 3: pair_sum_tile<3>(blk, stride, m, tb.t, tb.tile, acc); break;
-        case 4: pair_sum_tile<4>(blk, stride, m, tb.t, tb.tile, acc); break;
-        case 5: pair_sum_tile<5>(blk, stride, m, tb.t, tb.tile, acc); break;
-        case 6: pair_sum_tile<6>(blk, stride, m, tb.t, tb.tile, acc); break;
-        case 7: pair_sum_tile<7>(blk, stride, m, tb.t, tb.tile, acc); break;
-        default: pair_sum_tile<8>(blk, stride, m, tb.t, tb.tile, acc); break;
+    if (W <= kTileWords && table_ready(tb, jb, j, nbits + 1)) {
+        if (nbits <= jb.n_u58) {
+            switch (W) {
+            case 1: pair_sum_tile<1, true>(blk, stride, m, tb.t, tb.tile, acc); break;
+            case 2: pair_sum_tile<2, true>(blk, stride, m, tb.t, tb.tile, acc); break;
+            case 3: pair_sum_tile<3, true>(blk, stride, m, tb.t, tb.tile, acc); break;
+            default: pair_sum_tile<4, true>(blk, stride, m, tb.t, tb.tile, acc); break;
+            }
+        } else {
+            switch (W) {
+            case 1: pair_sum_tile<1, false>(blk, stride, m, tb.t, tb.tile, acc); break;
+            case 2: pair_sum_tile<2, false>(blk, stride, m, tb.t, tb.tile, acc); break;
+            case 3: pair_sum_tile<3, false>(blk, stride, m, tb.t, tb.tile, acc); break;
+            default: pair_sum_tile<4, false>(blk, stride, m, tb.t, tb.tile, acc); break;
+            }
         }
     } else {
         pair_sum_mem(blk, stride, m, W, jb.binom, jb.qA, jb.n_ovf, acc);
@@ -677,7 +706,19 @@ __device__ __forceinline__ uint64_t *arena_alloc(Arena &ar, uint64_t words, bool
 struct Counters {
     unsigned long long pair_words, filter_words;
     unsigned long long cyc_setup, cyc_compact, cyc_pair, cyc_filter;
+    unsigned long long pairs, pair_slots;
 };
+
+// Work of one pair_sum over m rows: pairs, and lane-slots the tiling spends.
+__device__ __forceinline__ void count_pairs(Counters &ct, uint32_t m, uint32_t W)
+{
+    const unsigned long long pr = (unsigned long long)m * (m - 1) / 2;
+    ct.pairs += pr;
+    ct.pair_words += pr * W;
+    for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize)
+        ct.pair_slots += (unsigned long long)(b0 / kWaveSize) * kWaveSize * kWaveSize +
+                         (unsigned long long)(min((uint32_t)kWaveSize, m - b0) - 1) * kWaveSize;
+}
 
 __device__ __forceinline__ uint64_t cycles() { return __builtin_amdgcn_s_memtime(); }
 
@@ -834,7 +875,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     if (m2 < pA - 2) return;
     if (pA == 4) {
         pair_sum(blk2, rem, m2, W2, s2n, jb, jidx, tb, acc);
-        ct.pair_words += (unsigned long long)m2 * (m2 - 1) / 2 * W2;
+        count_pairs(ct, m2, W2);
         if (instrument) ct.cyc_pair += cycles() - t0;
         return;
     }
@@ -889,7 +930,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         if (mc >= pA - d - 1) {
             if (d + 1 == pA - 2) {
                 pair_sum(nb, cap, mc, W2, s2n, jb, jidx, tb, acc);
-                ct.pair_words += (unsigned long long)mc * (mc - 1) / 2 * W2;
+                count_pairs(ct, mc, W2);
                 if (instrument) ct.cyc_pair += cycles() - t0;
             } else {
                 ++d;
@@ -914,6 +955,8 @@ __device__ void enum_flush(Slot *slots, uint32_t slot, Acc &acc, Counters &ct, b
         atomicAdd(&slots[slot].cyc_compact, ct.cyc_compact);
         atomicAdd(&slots[slot].cyc_pair, ct.cyc_pair);
         atomicAdd(&slots[slot].cyc_filter, ct.cyc_filter);
+        atomicAdd(&slots[slot].pairs, ct.pairs);
+        atomicAdd(&slots[slot].pair_slots, ct.pair_slots);
     }
     acc.v = 0;
     acc.ovf = false;
@@ -926,7 +969,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
 {
     __shared__ uint64_t lds[kWavesPerBlock][kLdsWordsPerWave];
     __shared__ uint64_t tbl[kWavesPerBlock][kTableLen];
-    __shared__ uint64_t tiles[kWavesPerBlock][kWaveSize * 8];
+    __shared__ uint64_t tiles[kWavesPerBlock][kWaveSize * kTileWords];
     const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
     const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     uint64_t *stack = &lds[wv][0];
