@@ -24,6 +24,12 @@ if ROOT not in sys.path:
 VALU_INT_PEAK = 256 * 4 * 16 * 2.4e9
 OPS_PER_WORD = 4   # 2 x v_and_b32 + 2 x v_bcnt_u32_b32 per 64-bit word pair
 
+# HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
+# 1 GiB device copy), valid only for the kernel source they were taken on.
+TRAFFIC_KERNEL_SHA256_PREFIX = "f91e8905877a1a3f"
+TRAFFIC_BYTES_Q44 = (932683 * 2.0 + 2915909 * 1.0) * 1024
+
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4)]),
     "small_er": ("small_er", [(3, 3)]),
@@ -58,6 +64,8 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=200, help="queries per arrival rate")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000")
     ap.add_argument("--serve-graphs", type=int, default=64)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -75,6 +83,15 @@ def main():
     gen_name, default_q = WORKLOADS[args.workload]
     queries = parse_queries(args.queries) if args.queries else default_q
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 18   # float32 elements
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read, {args.copy_calibration_mib} MiB written")
+        del src, dst
     t0 = time.time()
     g = getattr(gg, gen_name)()
     log(f"[bench] generated {args.workload}: {g.manifest['edges']} edges in {time.time() - t0:.1f}s")
@@ -169,11 +186,23 @@ def main():
         "root_vertices_per_s": roots / (ms_per_step / 1000),
         "per_query": per_query,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_INT_PEAK / 1e12,
-                     "unit": "Tintop/s", "frac": achieved / VALU_INT_PEAK, "traffic": None,
-                     "kernel": "k_enumerate"},
+                     "unit": "Tintop/s", "frac": achieved / VALU_INT_PEAK, "traffic": traffic_bytes(queries),
+                     "traffic_unit": "bytes per k_enumerate launch of (4,4)", "kernel": "k_enumerate"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def traffic_bytes(queries):
+    """Measured HBM bytes of the (4,4) enumeration launch, or None when the
+    kernel source changed since the counters were taken or (4,4) is not run."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2403_07858_amd", "csrc", "bc_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if not sha.startswith(TRAFFIC_KERNEL_SHA256_PREFIX) or (4, 4) not in queries:
+        return None
+    return TRAFFIC_BYTES_Q44
 
 
 def cpu_baseline(g, pq, n_roots, log):
