@@ -25,6 +25,7 @@ constexpr uint32_t kLdsWordsPerWave = 600;    // LDS arena per wavefront (64-bit
 constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of the tiled leaf sum
 constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
+constexpr uint32_t kTaskChunk = 4;            // consecutive tasks taken per queue pop
 
 
 uint32_t max_lds_words_per_wave() { return kLdsWordsPerWave; }
@@ -715,9 +716,9 @@ __device__ __forceinline__ void count_pairs(Counters &ct, uint32_t m, uint32_t W
     const unsigned long long pr = (unsigned long long)m * (m - 1) / 2;
     ct.pairs += pr;
     ct.pair_words += pr * W;
-    for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize)
+    for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize)   // full tiles, then the folded diagonal tile
         ct.pair_slots += (unsigned long long)(b0 / kWaveSize) * kWaveSize * kWaveSize +
-                         (unsigned long long)(min((uint32_t)kWaveSize, m - b0) - 1) * kWaveSize;
+                         (unsigned long long)(min((uint32_t)kWaveSize, m - b0) / 2) * kWaveSize;
 }
 
 __device__ __forceinline__ uint64_t cycles() { return __builtin_amdgcn_s_memtime(); }
@@ -816,6 +817,31 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     uint64_t *blk2 = arena_alloc(ar, (uint64_t)rem * W2, cap_fail);
     if (!blk2) return;
     uint32_t m2 = 0;
+    if (nz <= 2 && nz == W2) {
+        // Common case: S2 lives in at most two words that need no packing.
+        // The two masks stay in registers and the next chunk's row words are
+        // loaded before the current chunk is filtered.
+        const uint64_t s0 = nzt[0], s1 = (nz > 1) ? nzt[8] : 0ull;
+        const uint64_t *r0 = base + (uint64_t)(uint32_t)nzt[7] * k;
+        const uint64_t *r1 = base + (uint64_t)(uint32_t)((nz > 1) ? nzt[15] : nzt[7]) * k;
+        uint32_t b = i + 1 + ln;
+        uint64_t x0 = (b < k) ? r0[b] : 0ull, x1 = (nz > 1 && b < k) ? r1[b] : 0ull;
+        for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize, b += kWaveSize) {
+            const uint64_t v0 = x0 & s0, v1 = x1 & s1;
+            const uint32_t nb = b + kWaveSize;
+            x0 = (nb < k) ? r0[nb] : 0ull;
+            x1 = (nz > 1 && nb < k) ? r1[nb] : 0ull;
+            const uint32_t n = (uint32_t)(__popcll(v0) + __popcll(v1));
+            const bool keep = b < k && n >= q;
+            const uint64_t mask = __ballot(keep);
+            if (keep) {
+                const uint32_t idx = m2 + mbcnt64(mask);
+                blk2[idx] = v0;
+                if (nz > 1) blk2[(uint64_t)rem + idx] = v1;
+            }
+            m2 += (uint32_t)__popcll(mask);
+        }
+    } else
     for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
         const uint32_t b = b0 + ln;
         const bool valid = b < k;
@@ -827,7 +853,16 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         }
         const bool keep = valid && n >= q;
         const uint64_t mask = __ballot(keep);
-        if (mask) {
+        if (mask && nz == W2) {
+            // S2's nonzero words are already as few as its bits need: the
+            // masked words are the compacted row (word e = S2 word e's bits)
+            const uint32_t idx = m2 + mbcnt64(mask);
+            for (uint32_t e = 0; e < nz; ++e) {
+                const uint32_t w = (uint32_t)nzt[8ull * e + 7];
+                const uint64_t x = nzt[8ull * e] & base[(uint64_t)w * k + bb];
+                if (keep) blk2[(uint64_t)e * rem + idx] = x;
+            }
+        } else if (mask) {
             // every lane walks the same entries (uniform control flow); lanes
             // that do not keep their row write nothing
             const uint32_t idx = m2 + mbcnt64(mask);
@@ -994,29 +1029,35 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     Counters ct{};
     uint32_t cur_job = 0xffffffffu;
     for (;;) {
-        unsigned long long t = 0;
-        if (ln == 0) t = atomicAdd(prm.queue, 1ull);
-        t = bcast64(t, 0);
-        if (t >= prm.n_tasks) break;
-        // root owning task t: largest r with roots[r].task_begin <= t
-        uint32_t lo = 0, hi = prm.n_roots;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (prm.roots[mid].task_begin <= t) lo = mid;
+        // pop kTaskChunk consecutive tasks; only the first needs the root
+        // search, the rest advance through the (contiguous) task ranges
+        unsigned long long t0 = 0;
+        if (ln == 0) t0 = atomicAdd(prm.queue, (unsigned long long)kTaskChunk);
+        t0 = bcast64(t0, 0);
+        if (t0 >= prm.n_tasks) break;
+        const unsigned long long t_end = min(t0 + kTaskChunk, (unsigned long long)prm.n_tasks);
+        // root owning task t0: largest r with roots[r].task_begin <= t0
+        uint32_t r = 0, hi = prm.n_roots;
+        while (hi - r > 1) {
+            const uint32_t mid = (r + hi) >> 1;
+            if (prm.roots[mid].task_begin <= t0) r = mid;
             else hi = mid;
         }
-        const ActiveRoot rt = prm.roots[lo];
-        if (rt.job != cur_job) {
-            if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
-            cur_job = rt.job;
+        ActiveRoot rt = prm.roots[r];
+        for (unsigned long long t = t0; t < t_end; ++t) {
+            while (t >= rt.task_begin + rt.n_tasks) rt = prm.roots[++r];   // every active root owns >= 1 task
+            if (rt.job != cur_job) {
+                if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
+                cur_job = rt.job;
+            }
+            const Job jb = prm.jobs[rt.job];
+            bool cap_fail = false, timed_out = past_deadline(jb.deadline);
+            if (!timed_out)
+                run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct,
+                         instrument, &cap_fail, &timed_out);
+            if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
+            if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
         }
-        const Job jb = prm.jobs[rt.job];
-        bool cap_fail = false, timed_out = past_deadline(jb.deadline);
-        if (!timed_out)
-            run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct, instrument,
-                     &cap_fail, &timed_out);
-        if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
-        if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
     }
     if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
 }
