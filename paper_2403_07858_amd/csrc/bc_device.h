@@ -55,6 +55,7 @@ enum : unsigned {
     FLAG_CAPACITY = 2u,     // a scratch bound computed on the host was exceeded
     FLAG_MISMATCH = 4u,     // candidate count differs between the two wedge passes
     FLAG_TIMEOUT = 8u,      // the job's deadline passed before it finished
+    FLAG_POOL = 16u,        // the row pool was too small for some root (rows built again)
 };
 
 constexpr int kWaveSize = 64;
@@ -94,6 +95,14 @@ hipError_t launch_cand_count(const Job *jobs, const uint64_t *job_root_prefix, u
                              uint64_t total_roots, RootScratch scratch, uint32_t n_blocks,
                              unsigned long long *queue, uint32_t *out_k, Slot *slots,
                              hipStream_t stream);
+// Candidate counts and rows in one kernel; rows go to pool[out_off[r] ..]
+// (bump-allocated from counters[1], capacity pool_cap words; out_off = ~0 when
+// a root has no rows).  counters[0] is the root queue.  Needs 80 KiB of LDS
+// per block.
+hipError_t launch_root_build(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
+                             uint64_t total_roots, RootScratch scratch, uint64_t *pool, uint64_t pool_cap,
+                             uint32_t n_blocks, unsigned long long *counters, uint32_t *out_k, uint64_t *out_off,
+                             Slot *slots, hipStream_t stream);
 hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t n_roots,
                              uint64_t *pool, RootScratch scratch, uint32_t n_blocks,
                              unsigned long long *queue, Slot *slots, hipStream_t stream);

@@ -399,6 +399,27 @@ int cu_count(int device)
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0) v = 256;
         cache[device] = v;
+        // keep stream-ordered allocations cached between calls instead of
+        // returning them to the driver at every synchronization
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+            uint64_t thr = ~0ull;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    }
+    return cache[device];
+}
+
+int lds_per_block(int device)
+{
+    static std::mutex mu;
+    static std::vector<int> cache(64, -1);
+    std::lock_guard<std::mutex> g(mu);
+    if (device < 0 || device >= 64) return 0;
+    if (cache[device] < 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = 0;
+        cache[device] = v;
     }
     return cache[device];
 }
@@ -537,7 +558,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     BC_HIP(mem.get(&d_jobs, nj));
     BC_HIP(mem.get(&d_tab, tab_off[nj]));
     BC_HIP(mem.get(&d_slots, nj));
-    BC_HIP(mem.get(&d_queue, 4));
+    BC_HIP(mem.get(&d_queue, 8));
     {
         std::vector<u128> tab(tab_off[nj]);
         for (uint32_t j = 0; j < nj; ++j) {
@@ -549,7 +570,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         BC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
     }
     BC_HIP(bcdev::launch_fill_slots(d_slots, nj, st));
-    BC_HIP(fill_u32((uint32_t *)d_queue, 8, 0u, st));
+    BC_HIP(fill_u32((uint32_t *)d_queue, 16, 0u, st));
 
     Timer tm;
     tm.mark(0, st);
@@ -577,10 +598,17 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     }
     const uint64_t total_roots = root_prefix.back();
     std::vector<uint32_t> h_k(total_roots);
+    std::vector<uint64_t> h_off;
     bcdev::RootScratch rs{};
     const uint32_t root_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(total_roots, 1), (uint64_t)ncu * 2);
     std::vector<bcdev::Job> cjobs;
     bcdev::Job *d_cjobs = nullptr;
+    // The fused per-root kernel (LDS counting, rows bump-allocated on the
+    // device) needs 80 KiB of LDS per block and a pool sized up front; the
+    // two-kernel path (count, plan, rows) is the fallback.
+    const bool fused = lds_per_block(device) >= 84 * 1024;
+    uint64_t *d_pool_fused = nullptr;
+    uint64_t pool_cap = 0;
     if (total_roots) {
         // the candidate pass runs over its own compact job table
         cjobs.reserve(cj.size());
@@ -597,8 +625,23 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         BC_HIP(fill_u32(rs.cnt, (uint64_t)root_blocks * nA_max, 0u, st));
         BC_HIP(hipMemcpyAsync(d_cjobs, cjobs.data(), cjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
         BC_HIP(hipMemcpyAsync(d_rp, root_prefix.data(), root_prefix.size() * 8, hipMemcpyHostToDevice, st));
-        BC_HIP(bcdev::launch_cand_count(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, root_blocks, d_queue + 0,
-                                        d_k, d_slots, st));
+        if (fused) {
+            // room for the rows of every root: a generous multiple of the
+            // edges; a root that finds no room is rebuilt by the two-kernel path
+            uint64_t nnz_sum = 0;
+            for (uint32_t j : cj) nnz_sum += specs[jobs[j].spec].g->nnz;
+            pool_cap = std::max<uint64_t>(1ull << 22, 32 * nnz_sum + (4ull << 20));
+            uint64_t *d_off;
+            BC_HIP(mem.get(&d_off, total_roots));
+            BC_HIP(mem.get(&d_pool_fused, pool_cap));
+            BC_HIP(bcdev::launch_root_build(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, d_pool_fused, pool_cap,
+                                            root_blocks, d_queue + 4, d_k, d_off, d_slots, st));
+            h_off.resize(total_roots);
+            BC_HIP(hipMemcpyAsync(h_off.data(), d_off, total_roots * 8, hipMemcpyDeviceToHost, st));
+        } else {
+            BC_HIP(bcdev::launch_cand_count(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, root_blocks,
+                                            d_queue + 0, d_k, d_slots, st));
+        }
         BC_HIP(hipMemcpyAsync(h_k.data(), d_k, total_roots * 4, hipMemcpyDeviceToHost, st));
     }
     tm.mark(1, st);
@@ -635,6 +678,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         uint32_t c;  // index into cj / cjobs
         uint32_t root, k, w1;
         uint64_t cost;
+        uint64_t item;   // index of the root in the candidate pass
     };
     std::vector<Plan> plan;
     uint64_t cand_edges = 0;
@@ -652,17 +696,21 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             uint64_t x = k * w1;
             const uint32_t e = std::min<uint32_t>(hj.pA - 1, 3);
             for (uint32_t t = 1; t < e; ++t) x = std::min<uint64_t>(x * k, 1ull << 62);
-            plan.push_back(Plan{c, u, (uint32_t)k, w1, x});
+            plan.push_back(Plan{c, u, (uint32_t)k, w1, x, r});
         }
     }
     std::stable_sort(plan.begin(), plan.end(), [](const Plan &a, const Plan &b) { return a.cost > b.cost; });
     std::vector<bcdev::ActiveRoot> aroots(plan.size());
     uint64_t pool_words = 0, tasks = 0, slab_need = 64;
+    // rows already built by the fused kernel, unless some root found no room
+    bool rows_ready = fused;
+    for (const Plan &pl : plan)
+        if (fused && h_off[pl.item] == ~0ull) rows_ready = false;
     for (size_t r = 0; r < plan.size(); ++r) {
         const Plan &pl = plan[r];
         const uint32_t pA = cjobs[pl.c].pA;
         bcdev::ActiveRoot &a = aroots[r];
-        a.pool_off = pool_words;
+        a.pool_off = rows_ready ? h_off[pl.item] : pool_words;
         a.task_begin = tasks;
         a.job = pl.c;
         a.root = pl.root;
@@ -682,13 +730,15 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     tm.mark(2, st);
     if (!plan.empty()) {
         bcdev::ActiveRoot *d_roots;
-        uint64_t *d_pool;
+        uint64_t *d_pool = d_pool_fused;
         BC_HIP(mem.get(&d_roots, aroots.size()));
-        BC_HIP(mem.get(&d_pool, pool_words));
         BC_HIP(hipMemcpyAsync(d_roots, aroots.data(), aroots.size() * sizeof(bcdev::ActiveRoot), hipMemcpyHostToDevice,
                               st));
-        BC_HIP(bcdev::launch_rows_build(d_cjobs, d_roots, (uint32_t)aroots.size(), d_pool, rs, root_blocks, d_queue + 1,
-                                        d_slots, st));
+        if (!rows_ready) {
+            BC_HIP(mem.get(&d_pool, pool_words));
+            BC_HIP(bcdev::launch_rows_build(d_cjobs, d_roots, (uint32_t)aroots.size(), d_pool, rs, root_blocks,
+                                            d_queue + 1, d_slots, st));
+        }
         tm.mark(3, st);
         // Enumeration grid: waves_per_cu wavefronts per CU; each wave owns a
         // slab big enough for the deepest task of this plan.

@@ -469,6 +469,224 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
+// k_root_build: the candidate count and the candidate rows of every root in
+// one kernel.  Common-neighbour counts live in an LDS open-addressing table
+// (key w + 1 in the high half of a 64-bit entry, count in the low half);
+// roots whose distinct 2-hop vertices do not fit fall back to the per-block
+// dense counter array in HBM.  Row storage is taken from the pool with one
+// atomic bump per root, so counting and row building need no host round trip
+// in between.
+
+constexpr uint32_t kHashSlots = 8192;       // 64 KiB of LDS
+constexpr uint32_t kHashProbes = 128;       // longest probe sequence before falling back
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 13); }
+
+// Adds one to w's count; false when the table is too full (probe limit).
+__device__ __forceinline__ bool hash_inc(unsigned long long *tab, uint32_t w)
+{
+    const unsigned long long key = (unsigned long long)(w + 1u) << 32;
+    uint32_t h = hash_slot(w);
+    for (uint32_t p = 0; p < kHashProbes; ++p, h = (h + 1) & (kHashSlots - 1)) {
+        unsigned long long e = tab[h];
+        if ((e & 0xffffffff00000000ull) == 0) {
+            const unsigned long long old = atomicCAS(&tab[h], 0ull, key | 1ull);
+            if (old == 0) return true;
+            e = old;
+        }
+        if ((e & 0xffffffff00000000ull) == key) {
+            atomicAdd(&tab[h], 1ull);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Index of w's entry (w must be present).
+__device__ __forceinline__ uint32_t hash_find(const unsigned long long *tab, uint32_t w)
+{
+    const unsigned long long key = (unsigned long long)(w + 1u) << 32;
+    uint32_t h = hash_slot(w);
+    while ((tab[h] & 0xffffffff00000000ull) != key) h = (h + 1) & (kHashSlots - 1);
+    return h;
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_root_build(const Job *jobs, const uint64_t *job_root_prefix,
+                                                              uint32_t n_jobs, uint64_t total_roots,
+                                                              RootScratch sc, uint64_t *pool, uint64_t pool_cap,
+                                                              unsigned long long *counters, uint32_t *out_k,
+                                                              uint64_t *out_off, Slot *slots)
+{
+    __shared__ unsigned long long s_tab[kHashSlots];
+    __shared__ uint32_t s_cand[kSortCap];
+    __shared__ unsigned long long s_item, s_off;
+    __shared__ uint32_t s_k, s_nt, s_flag;
+    unsigned long long *queue = counters;        // roots
+    unsigned long long *pool_head = counters + 1;
+    uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
+    uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
+    uint32_t *cand_g = sc.cand + (uint64_t)blockIdx.x * sc.stride;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) s_tab[x] = 0;
+    u128 acc = 0;
+    bool ovf = false;
+    uint32_t cur_job = 0xffffffffu;
+    for (;;) {
+        if (tid == 0) {
+            s_item = atomicAdd(queue, 1ull);
+            s_k = 0;
+            s_nt = 0;
+            s_flag = 0;
+            s_off = ~0ull;
+        }
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= total_roots) break;
+        const uint32_t j = find_segment(job_root_prefix, n_jobs, item);
+        if (j != cur_job) {
+            if (cur_job != 0xffffffffu) wave_flush(slots, jobs[cur_job].slot, acc, ovf, 0, 0);
+            acc = 0;
+            ovf = false;
+            cur_job = j;
+        }
+        const Job jb = jobs[j];
+        const uint32_t u = jb.root_lo + (uint32_t)(item - job_root_prefix[j]);
+        const uint64_t ub = jb.ptrA[u];
+        const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - ub);
+        const uint32_t W1 = (du + 63) >> 6;
+        // one thread reads the clock so that the whole block takes the same branch
+        if (tid == 0 && past_deadline(jb.deadline)) {
+            s_flag = 4;
+            atomicOr(&slots[jb.slot].flags, FLAG_TIMEOUT);
+        }
+        __syncthreads();
+        if (du < jb.qA || s_flag == 4) {
+            if (tid == 0) {
+                out_k[item] = 0;
+                out_off[item] = ~0ull;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        // pass 1: common-neighbour counts, in LDS while they fit
+        oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
+            if (!hash_inc(s_tab, w)) s_flag = 1;
+        });
+        __syncthreads();
+        const bool in_lds = s_flag == 0;
+        if (!in_lds) {
+            // too many distinct 2-hop vertices: count again in the dense array
+            for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) s_tab[x] = 0;
+            oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
+                if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
+            });
+            __syncthreads();
+        }
+        // candidates: count >= qA (pA == 2 sums its leaves here)
+        const bool rows = jb.pA >= 3;
+        if (in_lds) {
+            for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) {
+                const unsigned long long e = s_tab[x];
+                const uint32_t c = (uint32_t)e;
+                if ((e >> 32) != 0 && c >= jb.qA) {
+                    const uint32_t s = atomicAdd(&s_k, 1u);
+                    if (rows) {
+                        if (s < kSortCap) s_cand[s] = (uint32_t)(e >> 32) - 1u;
+                        cand_g[s] = (uint32_t)(e >> 32) - 1u;
+                    } else {
+                        if (c >= jb.n_ovf) ovf = true;
+                        else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                    }
+                }
+            }
+        } else {
+            const uint32_t nt = s_nt;
+            for (uint32_t t = tid; t < nt; t += kBlockThreads) {
+                const uint32_t w = touched[t];
+                const uint32_t c = atomicAdd(&cnt[w], 0u);
+                if (c >= jb.qA) {
+                    const uint32_t s = atomicAdd(&s_k, 1u);
+                    if (rows) {
+                        if (s < kSortCap) s_cand[s] = w;
+                        cand_g[s] = w;
+                    } else {
+                        if (c >= jb.n_ovf) ovf = true;
+                        else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                        atomicExch(&cnt[w], 0u);
+                    }
+                } else {
+                    atomicExch(&cnt[w], 0u);
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t k = s_k;
+        const bool build = rows && k >= jb.pA - 1;
+        if (build && tid == 0) {
+            const unsigned long long need = (unsigned long long)k * W1;
+            const unsigned long long off = atomicAdd(pool_head, need);
+            if (off + need <= pool_cap) s_off = off;
+        }
+        __syncthreads();
+        const uint64_t off = s_off;
+        if (build && off != ~0ull) {
+            uint64_t *base = pool + off;
+            uint32_t *cand = (k <= (uint32_t)kSortCap) ? s_cand : cand_g;
+            if (k <= (uint32_t)kSortCap) block_sort_u32(s_cand, k);
+            __syncthreads();
+            // mark each candidate with its row index
+            for (uint32_t s = tid; s < k; s += kBlockThreads) {
+                if (in_lds) {
+                    const uint32_t h = hash_find(s_tab, cand[s]);
+                    s_tab[h] = (s_tab[h] & 0xffffffff00000000ull) | kSlotFlag | s;
+                } else {
+                    atomicExch(&cnt[cand[s]], kSlotFlag | s);
+                }
+            }
+            const uint64_t words = (uint64_t)k * W1;
+            for (uint64_t x = tid; x < words; x += kBlockThreads) base[x] = 0;
+            __threadfence();
+            __syncthreads();
+            // pass 2: set bit j of row(w) for every wedge u - v_j - w with w a candidate
+            oriented_wedges(jb, u, ub, du, [&](uint32_t jj, uint32_t w) {
+                const uint32_t e = in_lds ? (uint32_t)s_tab[hash_find(s_tab, w)] : atomicAdd(&cnt[w], 0u);
+                if (e & kSlotFlag)
+                    atomicOr((unsigned long long *)&base[(uint64_t)(jj >> 6) * k + (e & ~kSlotFlag)],
+                             1ull << (jj & 63));
+            });
+            __syncthreads();
+            if (!in_lds)
+                for (uint32_t s = tid; s < k; s += kBlockThreads) atomicExch(&cnt[cand[s]], 0u);
+        } else if (rows && !in_lds) {
+            // no rows wanted (or no pool room): clear the candidates' counters
+            const uint32_t kk = min(k, sc.stride > 0 ? (uint32_t)sc.stride : 0u);
+            for (uint32_t s = tid; s < kk; s += kBlockThreads) atomicExch(&cnt[cand_g[s]], 0u);
+        }
+        if (build && off == ~0ull && tid == 0) atomicOr(&slots[jb.slot].flags, FLAG_POOL);
+        if (tid == 0) {
+            out_k[item] = k;
+            out_off[item] = build ? off : ~0ull;
+        }
+        if (in_lds)
+            for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) s_tab[x] = 0;
+        __syncthreads();
+    }
+    if (cur_job != 0xffffffffu) wave_flush(slots, jobs[cur_job].slot, acc, ovf, 0, 0);
+}
+
+hipError_t launch_root_build(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
+                             uint64_t total_roots, RootScratch scratch, uint64_t *pool, uint64_t pool_cap,
+                             uint32_t n_blocks, unsigned long long *counters, uint32_t *out_k, uint64_t *out_off,
+                             Slot *slots, hipStream_t stream)
+{
+    if (total_roots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_root_build, dim3(n_blocks), dim3(kBlockThreads), 0, stream, jobs, job_root_prefix, n_jobs,
+                       total_roots, scratch, pool, pool_cap, counters, out_k, out_off, slots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Enumeration.
 
 // Per-lane leaf accumulators.  The u128 total takes the fallback path (table
