@@ -15,6 +15,7 @@ typedef unsigned __int128 u128;
 struct Job {
     const uint64_t *ptrA;   // nA + 1
     const uint32_t *adjA;   // N(u) as sorted B ids
+    const uint32_t *rposA;  // per edge u - v of adjA: position of u within N(v)
     const uint64_t *ptrB;   // nB + 1
     const uint32_t *adjB;   // N(v) as sorted A ids
     const u128 *binom;      // binom[n] = C(n, qA) for n in [0, binom_n)
@@ -62,6 +63,8 @@ constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlockThreads = kWaveSize * kWavesPerBlock;
 constexpr int kSortCap = 4096;          // candidates sorted in LDS up to this many
+constexpr int kRbWaves = 16;            // waves per block of the fused per-root kernel
+constexpr int kRbThreads = kWaveSize * kRbWaves;
 constexpr uint32_t kSlotFlag = 0x80000000u;
 
 struct RootScratch {
@@ -97,8 +100,8 @@ hipError_t launch_cand_count(const Job *jobs, const uint64_t *job_root_prefix, u
                              hipStream_t stream);
 // Candidate counts and rows in one kernel; rows go to pool[out_off[r] ..]
 // (bump-allocated from counters[1], capacity pool_cap words; out_off = ~0 when
-// a root has no rows).  counters[0] is the root queue.  Needs 80 KiB of LDS
-// per block.
+// a root has no rows).  counters[0] is the root queue.  Blocks of kRbThreads
+// threads with 144 KiB of LDS each.
 hipError_t launch_root_build(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
                              uint64_t total_roots, RootScratch scratch, uint64_t *pool, uint64_t pool_cap,
                              uint32_t n_blocks, unsigned long long *counters, uint32_t *out_k, uint64_t *out_off,

@@ -74,6 +74,7 @@ struct Side {
     std::vector<uint64_t> h_ptr;     // relabelled CSR on the host (by rank)
     uint64_t *d_ptr = nullptr;
     uint32_t *d_adj = nullptr;
+    uint32_t *d_rpos = nullptr;      // per edge (a, b): position of a within N(b)
 };
 
 }  // namespace
@@ -185,8 +186,10 @@ void free_side(Side &s)
 {
     if (s.d_ptr) (void)hipFree(s.d_ptr);
     if (s.d_adj) (void)hipFree(s.d_adj);
+    if (s.d_rpos) (void)hipFree(s.d_rpos);
     s.d_ptr = nullptr;
     s.d_adj = nullptr;
+    s.d_rpos = nullptr;
 }
 
 }  // namespace
@@ -231,19 +234,37 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
     const std::vector<uint32_t> *rows[2] = {&rowsU, &rowsV};
     const std::vector<uint32_t> *ids[2] = {&idU, &idV};
     hipStream_t st = pick_stream(opts);
+    std::vector<uint32_t> adj[2], rpos[2];
     for (int s = 0; s < 2; ++s) {
         Side &sd = g->side[s];
         sd.n = cs[s]->n_rows;
-        std::vector<uint32_t> adj;
-        relabel(cs[s], *rows[s], *ids[s], g->side[1 - s].rank_of, sd.h_ptr, adj);
+        relabel(cs[s], *rows[s], *ids[s], g->side[1 - s].rank_of, sd.h_ptr, adj[s]);
         for (uint64_t r = 0; r < sd.n; ++r)
             sd.max_deg = std::max<uint32_t>(sd.max_deg, (uint32_t)(sd.h_ptr[r + 1] - sd.h_ptr[r]));
+    }
+    // Reverse positions: for the edge (a, b) stored in a's row, the index of a
+    // within b's row.  Visiting b in increasing order meets a's edges in the
+    // order a's sorted row stores them, so one cursor per a suffices.
+    for (int s = 0; s < 2; ++s) {
+        const Side &sa = g->side[s], &sb = g->side[1 - s];
+        rpos[s].resize(g->nnz);
+        std::vector<uint64_t> cursor(sa.h_ptr.begin(), sa.h_ptr.end() - 1);
+        for (uint64_t b = 0; b < sb.n; ++b)
+            for (uint64_t i = sb.h_ptr[b]; i < sb.h_ptr[b + 1]; ++i)
+                rpos[s][cursor[adj[1 - s][i]]++] = (uint32_t)(i - sb.h_ptr[b]);
+    }
+    for (int s = 0; s < 2; ++s) {
+        Side &sd = g->side[s];
+        const uint64_t m = std::max<uint64_t>(1, g->nnz) * sizeof(uint32_t);
         hipError_t e = hipMalloc(&sd.d_ptr, (sd.n + 1) * sizeof(uint64_t));
-        if (e == hipSuccess) e = hipMalloc(&sd.d_adj, std::max<uint64_t>(1, g->nnz) * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&sd.d_adj, m);
+        if (e == hipSuccess) e = hipMalloc(&sd.d_rpos, m);
         if (e == hipSuccess)
             e = hipMemcpyAsync(sd.d_ptr, sd.h_ptr.data(), (sd.n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess && g->nnz)
-            e = hipMemcpyAsync(sd.d_adj, adj.data(), g->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+            e = hipMemcpyAsync(sd.d_adj, adj[s].data(), g->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && g->nnz)
+            e = hipMemcpyAsync(sd.d_rpos, rpos[s].data(), g->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             free_side(g->side[0]);
@@ -526,6 +547,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         memset(&d, 0, sizeof(d));
         d.ptrA = A.d_ptr;
         d.adjA = A.d_adj;
+        d.rposA = A.d_rpos;
         d.ptrB = g->side[1 - hj.anchor].d_ptr;
         d.adjB = g->side[1 - hj.anchor].d_adj;
         d.nA = (uint32_t)A.n;
@@ -604,9 +626,9 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     std::vector<bcdev::Job> cjobs;
     bcdev::Job *d_cjobs = nullptr;
     // The fused per-root kernel (LDS counting, rows bump-allocated on the
-    // device) needs 80 KiB of LDS per block and a pool sized up front; the
+    // device) needs 144 KiB of LDS per block and a pool sized up front; the
     // two-kernel path (count, plan, rows) is the fallback.
-    const bool fused = lds_per_block(device) >= 84 * 1024;
+    const bool fused = lds_per_block(device) >= 148 * 1024;
     uint64_t *d_pool_fused = nullptr;
     uint64_t pool_cap = 0;
     if (total_roots) {
@@ -634,8 +656,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             uint64_t *d_off;
             BC_HIP(mem.get(&d_off, total_roots));
             BC_HIP(mem.get(&d_pool_fused, pool_cap));
+            // one block of kRbThreads per CU (its LDS table takes most of the CU's LDS)
+            const uint32_t fused_blocks = (uint32_t)std::min<uint64_t>(total_roots, (uint64_t)ncu);
             BC_HIP(bcdev::launch_root_build(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, d_pool_fused, pool_cap,
-                                            root_blocks, d_queue + 4, d_k, d_off, d_slots, st));
+                                            fused_blocks, d_queue + 4, d_k, d_off, d_slots, st));
             h_off.resize(total_roots);
             BC_HIP(hipMemcpyAsync(h_off.data(), d_off, total_roots * 8, hipMemcpyDeviceToHost, st));
         } else {

@@ -152,17 +152,6 @@ hipError_t launch_read_clock(uint64_t *out, hipStream_t stream)
     return hipGetLastError();
 }
 
-// First index in [b, e) whose value is > key (values sorted ascending).
-__device__ __forceinline__ uint64_t upper_bound_u32(const uint32_t *a, uint64_t b, uint64_t e, uint32_t key)
-{
-    while (b < e) {
-        uint64_t mid = b + ((e - b) >> 1);
-        if (a[mid] <= key) b = mid + 1;
-        else e = mid;
-    }
-    return b;
-}
-
 // Largest j in [0, n) with prefix[j] <= x (prefix nondecreasing, prefix[0] == 0).
 __device__ __forceinline__ uint32_t find_segment(const uint64_t *prefix, uint32_t n, uint64_t x)
 {
@@ -247,19 +236,60 @@ hipError_t launch_degree_sum(const Job *jobs, const uint32_t *job_ids, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Wedge scan shared by the two per-root kernels: for every neighbour v_j of u
-// (j = local id) and every w in N(v_j) with w > u, call f(j, w).  Waves take
-// the j's round robin; lanes stride over the oriented part of N(v_j).
-
+// Wedge scan shared by the two-kernel per-root path: for every neighbour v_j
+// of u (j = local id) and every w in N(v_j) with w > u, call f(j, w).  Waves
+// take the j's round robin; lanes stride over the oriented part of N(v_j),
+// which starts right after u (its position within N(v_j) is stored per edge).
 template <typename F>
 __device__ __forceinline__ void oriented_wedges(const Job &jb, uint32_t u, uint64_t ub, uint32_t du, F f)
 {
     const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
     for (uint32_t j = wv; j < du; j += kWavesPerBlock) {
         const uint32_t v = jb.adjA[ub + j];
-        const uint64_t vb = jb.ptrB[v], ve = jb.ptrB[v + 1];
-        const uint64_t s = upper_bound_u32(jb.adjB, vb, ve, u);
+        const uint64_t s = jb.ptrB[v] + jb.rposA[ub + j] + 1, ve = jb.ptrB[v + 1];
         for (uint64_t x = s + ln; x < ve; x += kWaveSize) f(j, jb.adjB[x]);
+    }
+}
+
+// The same wedges spread evenly over the NW waves of a block.  The
+// neighbours of u are taken 64 at a time, one per lane; a wave scan lays the
+// 64 oriented parts of their rows end to end, and the waves take 64-element
+// windows of that concatenation round robin, two windows per step.  Each lane
+// finds the part holding its element by a binary search over the lanes'
+// exclusive offsets.
+template <int NW, typename F>
+__device__ __forceinline__ void wedges_flat(const Job &jb, uint64_t ub, uint32_t du, F f)
+{
+    const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
+    for (uint32_t j0 = 0; j0 < du; j0 += kWaveSize) {
+        const uint32_t j = j0 + ln;
+        uint64_t s = 0;
+        uint32_t len = 0;
+        if (j < du) {
+            const uint32_t v = jb.adjA[ub + j];
+            s = jb.ptrB[v] + jb.rposA[ub + j] + 1;
+            len = (uint32_t)(jb.ptrB[v + 1] - s);
+        }
+        const uint32_t inc = wave_inclusive_scan(len);
+        const uint32_t excl = inc - len;
+        const uint64_t base = s - excl;   // element x of this lane's part is adjB[base + x] (mod 2^64)
+        const uint32_t total = __shfl(inc, kWaveSize - 1);
+        for (uint32_t x0 = wv * kWaveSize; x0 < total; x0 += 2 * NW * kWaveSize) {
+            const uint32_t xa = x0 + ln, xb = xa + NW * kWaveSize;
+            uint32_t la = 0, lb = 0;
+#pragma unroll
+            for (uint32_t b = 32; b; b >>= 1) {
+                // la + b <= 63: the larger steps already taken add up to at most 64 - 2b
+                if (__shfl(excl, (int)(la + b)) <= xa) la += b;
+                if (__shfl(excl, (int)(lb + b)) <= xb) lb += b;
+            }
+            const uint64_t pa = bcast64(base, (int)la) + xa, pb = bcast64(base, (int)lb) + xb;
+            uint32_t wa = 0, wb = 0;
+            if (xa < total) wa = jb.adjB[pa];
+            if (xb < total) wb = jb.adjB[pb];
+            if (xa < total) f(j0 + la, wa);
+            if (xb < total) f(j0 + lb, wb);
+        }
     }
 }
 
@@ -343,16 +373,18 @@ hipError_t launch_cand_count(const Job *jobs, const uint64_t *job_root_prefix, u
     return hipGetLastError();
 }
 
-// Block-wide bitonic sort of s[0, n) ascending, n <= kSortCap; pads to a power of two.
+// Block-wide bitonic sort of s[0, n) ascending by a block of NT threads;
+// pads to a power of two, so s must hold that many entries.
+template <int NT>
 __device__ void block_sort_u32(uint32_t *s, uint32_t n)
 {
     uint32_t n2 = 1;
     while (n2 < n) n2 <<= 1;
-    for (uint32_t i = n + threadIdx.x; i < n2; i += kBlockThreads) s[i] = 0xffffffffu;
+    for (uint32_t i = n + threadIdx.x; i < n2; i += NT) s[i] = 0xffffffffu;
     __syncthreads();
     for (uint32_t size = 2; size <= n2; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t pr = threadIdx.x; pr < (n2 >> 1); pr += kBlockThreads) {
+            for (uint32_t pr = threadIdx.x; pr < (n2 >> 1); pr += NT) {
                 const uint32_t i = 2 * stride * (pr / stride) + (pr % stride);
                 const uint32_t l = i + stride;
                 const bool asc = (i & size) == 0;
@@ -438,7 +470,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_build(const Job *jobs, c
             __syncthreads();
             continue;
         }
-        if (in_lds) block_sort_u32(s_cand, k);
+        if (in_lds) block_sort_u32<kBlockThreads>(s_cand, k);
         __syncthreads();
         for (uint32_t s = tid; s < k; s += kBlockThreads) atomicExch(&cnt[cand[s]], kSlotFlag | s);
         const uint64_t words = (uint64_t)k * W1;
@@ -470,55 +502,80 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
 
 // ---------------------------------------------------------------------------
 // k_root_build: the candidate count and the candidate rows of every root in
-// one kernel.  Common-neighbour counts live in an LDS open-addressing table
-// (key w + 1 in the high half of a 64-bit entry, count in the low half);
-// roots whose distinct 2-hop vertices do not fit fall back to the per-block
-// dense counter array in HBM.  Row storage is taken from the pool with one
-// atomic bump per root, so counting and row building need no host round trip
-// in between.
+// one kernel, one root per block of kRbWaves waves at a time.
+//
+// The 2-hop vertices of u live in an LDS open-addressing table (key w + 1,
+// linear probing).  When u has at most 64 neighbours (one row word), the
+// table entry accumulates w's row itself -- bit j set for the wedge u - v_j -
+// w -- so one wedge pass yields both |N(u) n N(w)| (the popcount) and the row.
+// Wider roots count in the first pass, index their candidates, and set the
+// row bits in a second pass into LDS (or the pool when the rows do not fit).
+// Roots whose 2-hop set overflows the table fall back to the per-block dense
+// counter array in HBM.  Row storage is taken from the pool with one atomic
+// bump per root, so counting and row building need no host round trip.
 
-constexpr uint32_t kHashSlots = 8192;       // 64 KiB of LDS
+constexpr uint32_t kHashSlots = 8192;       // LDS table entries
 constexpr uint32_t kHashProbes = 128;       // longest probe sequence before falling back
+constexpr uint32_t kSlotsPerThread = kHashSlots / kRbThreads;
+constexpr uint16_t kNoRow = 0xffffu;
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 13); }
 
-// Adds one to w's count; false when the table is too full (probe limit).
-__device__ __forceinline__ bool hash_inc(unsigned long long *tab, uint32_t w)
+// Slot of w, inserting it if new; -1 when the probe limit is reached.
+__device__ __forceinline__ int hash_insert(uint32_t *key, uint32_t w)
 {
-    const unsigned long long key = (unsigned long long)(w + 1u) << 32;
+    const uint32_t kv = w + 1u;
     uint32_t h = hash_slot(w);
     for (uint32_t p = 0; p < kHashProbes; ++p, h = (h + 1) & (kHashSlots - 1)) {
-        unsigned long long e = tab[h];
-        if ((e & 0xffffffff00000000ull) == 0) {
-            const unsigned long long old = atomicCAS(&tab[h], 0ull, key | 1ull);
-            if (old == 0) return true;
-            e = old;
-        }
-        if ((e & 0xffffffff00000000ull) == key) {
-            atomicAdd(&tab[h], 1ull);
-            return true;
+        const uint32_t e = key[h];
+        if (e == kv) return (int)h;
+        if (e == 0u) {
+            const uint32_t old = atomicCAS(&key[h], 0u, kv);
+            if (old == 0u || old == kv) return (int)h;
         }
     }
-    return false;
+    return -1;
 }
 
-// Index of w's entry (w must be present).
-__device__ __forceinline__ uint32_t hash_find(const unsigned long long *tab, uint32_t w)
+// Slot of w (w must be present).
+__device__ __forceinline__ uint32_t hash_find(const uint32_t *key, uint32_t w)
 {
-    const unsigned long long key = (unsigned long long)(w + 1u) << 32;
+    const uint32_t kv = w + 1u;
     uint32_t h = hash_slot(w);
-    while ((tab[h] & 0xffffffff00000000ull) != key) h = (h + 1) & (kHashSlots - 1);
+    while (key[h] != kv) h = (h + 1) & (kHashSlots - 1);
     return h;
 }
 
-__global__ __launch_bounds__(kBlockThreads) void k_root_build(const Job *jobs, const uint64_t *job_root_prefix,
-                                                              uint32_t n_jobs, uint64_t total_roots,
-                                                              RootScratch sc, uint64_t *pool, uint64_t pool_cap,
-                                                              unsigned long long *counters, uint32_t *out_k,
-                                                              uint64_t *out_off, Slot *slots)
+// Exclusive prefix of v over the block (thread order); *total gets the sum.
+// Uses s_wsum[kRbWaves]; the caller separates consecutive uses by a barrier.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wsum, uint32_t *total)
 {
-    __shared__ unsigned long long s_tab[kHashSlots];
-    __shared__ uint32_t s_cand[kSortCap];
+    const uint32_t wv = threadIdx.x / kWaveSize;
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (lane_id() == kWaveSize - 1) s_wsum[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < (uint32_t)kRbWaves; ++w) {
+        const uint32_t t = s_wsum[w];
+        before += w < wv ? t : 0u;
+        tot += t;
+    }
+    *total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, const uint64_t *job_root_prefix,
+                                                           uint32_t n_jobs, uint64_t total_roots, RootScratch sc,
+                                                           uint64_t *pool, uint64_t pool_cap,
+                                                           unsigned long long *counters, uint32_t *out_k,
+                                                           uint64_t *out_off, Slot *slots)
+{
+    __shared__ uint32_t s_key[kHashSlots];               // w + 1, 0 = empty
+    __shared__ unsigned long long s_row[kHashSlots];     // row word or count of the slot; later LDS rows
+    __shared__ uint16_t s_map[kHashSlots];               // row index of the slot's vertex, kNoRow if none
+    __shared__ uint32_t s_sort[kHashSlots];              // candidates being sorted
+    __shared__ uint32_t s_wsum[kRbWaves];
     __shared__ unsigned long long s_item, s_off;
     __shared__ uint32_t s_k, s_nt, s_flag;
     unsigned long long *queue = counters;        // roots
@@ -527,7 +584,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_root_build(const Job *jobs, c
     uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
     uint32_t *cand_g = sc.cand + (uint64_t)blockIdx.x * sc.stride;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) s_tab[x] = 0;
+    const uint32_t h0 = tid * kSlotsPerThread;   // this thread's slots in the per-root scans
+    for (uint32_t x = tid; x < kHashSlots; x += kRbThreads) {
+        s_key[x] = 0;
+        s_row[x] = 0;
+    }
     u128 acc = 0;
     bool ovf = false;
     uint32_t cur_job = 0xffffffffu;
@@ -568,48 +629,104 @@ __global__ __launch_bounds__(kBlockThreads) void k_root_build(const Job *jobs, c
             __syncthreads();
             continue;
         }
+        const bool one = W1 == 1;
+        const bool rows = jb.pA >= 3;
 
-        // pass 1: common-neighbour counts, in LDS while they fit
-        oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
-            if (!hash_inc(s_tab, w)) s_flag = 1;
+        // pass 1: insert every 2-hop vertex; one-word roots OR in the row bit,
+        // wider ones count
+        wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t jj, uint32_t w) {
+            const int h = hash_insert(s_key, w);
+            if (h < 0) s_flag = 1;
+            else if (one) atomicOr(&s_row[h], 1ull << jj);
+            else atomicAdd(&s_row[h], 1ull);
         });
         __syncthreads();
         const bool in_lds = s_flag == 0;
-        if (!in_lds) {
-            // too many distinct 2-hop vertices: count again in the dense array
-            for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) s_tab[x] = 0;
-            oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
-                if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
-            });
-            __syncthreads();
-        }
-        // candidates: count >= qA (pA == 2 sums its leaves here)
-        const bool rows = jb.pA >= 3;
+        uint32_t k = 0;
+        uint64_t off = ~0ull;
+        bool build = false;
         if (in_lds) {
-            for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) {
-                const unsigned long long e = s_tab[x];
-                const uint32_t c = (uint32_t)e;
-                if ((e >> 32) != 0 && c >= jb.qA) {
-                    const uint32_t s = atomicAdd(&s_k, 1u);
-                    if (rows) {
-                        if (s < kSortCap) s_cand[s] = (uint32_t)(e >> 32) - 1u;
-                        cand_g[s] = (uint32_t)(e >> 32) - 1u;
-                    } else {
-                        if (c >= jb.n_ovf) ovf = true;
-                        else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
-                    }
+            // candidates: count >= qA, indexed in slot order (pA == 2 sums its leaves here)
+            uint32_t mine = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kSlotsPerThread; ++i) {
+                const uint32_t h = h0 + i;
+                const unsigned long long e = s_row[h];
+                const uint32_t c = one ? (uint32_t)__popcll(e) : (uint32_t)e;
+                if (s_key[h] != 0u && c >= jb.qA) {
+                    ++mine;
+                    if (rows) continue;
+                    if (c >= jb.n_ovf) ovf = true;
+                    else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                }
+            }
+            uint32_t pos = block_excl_scan(mine, s_wsum, &k);
+            build = rows && k >= jb.pA - 1;
+            if (build && tid == 0) {
+                const unsigned long long need = (unsigned long long)k * W1;
+                const unsigned long long o = atomicAdd(pool_head, need);
+                if (o + need <= pool_cap) s_off = o;
+            }
+            __syncthreads();
+            off = s_off;
+            if (build && off != ~0ull) {
+                // rows in increasing rank order of the candidates: list and sort them
+#pragma unroll
+                for (uint32_t i = 0; i < kSlotsPerThread; ++i) {
+                    const uint32_t h = h0 + i;
+                    const unsigned long long e = s_row[h];
+                    const uint32_t c = one ? (uint32_t)__popcll(e) : (uint32_t)e;
+                    const uint32_t kv = s_key[h];
+                    const bool cand = kv != 0u && c >= jb.qA;
+                    if (cand) s_sort[pos++] = kv - 1u;
+                    if (!one) s_map[h] = kNoRow;
+                }
+                block_sort_u32<kRbThreads>(s_sort, k);
+                // one-word roots write their rows now; wider ones record the row index
+                for (uint32_t x = tid; x < k; x += kRbThreads) {
+                    const uint32_t h = hash_find(s_key, s_sort[x]);
+                    if (one) pool[off + x] = s_row[h];
+                    else s_map[h] = (uint16_t)x;
+                }
+                if (!one) {
+                    const uint64_t words = (uint64_t)k * W1;
+                    const bool lds_rows = words <= kHashSlots;
+                    __syncthreads();   // every count has been read
+                    if (lds_rows)
+                        for (uint32_t x = tid; x < words; x += kRbThreads) s_row[x] = 0;
+                    else
+                        for (uint64_t x = tid; x < words; x += kRbThreads) pool[off + x] = 0;
+                    __threadfence();
+                    __syncthreads();
+                    // pass 2: set bit j of row(w) for every wedge u - v_j - w with w a candidate
+                    wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t jj, uint32_t w) {
+                        const uint32_t m = s_map[hash_find(s_key, w)];
+                        if (m != kNoRow) {
+                            const uint64_t x = (uint64_t)(jj >> 6) * k + m;
+                            if (lds_rows) atomicOr(&s_row[x], 1ull << (jj & 63));
+                            else atomicOr((unsigned long long *)&pool[off + x], 1ull << (jj & 63));
+                        }
+                    });
+                    __syncthreads();
+                    if (lds_rows)
+                        for (uint32_t x = tid; x < words; x += kRbThreads) pool[off + x] = s_row[x];
                 }
             }
         } else {
+            // too many distinct 2-hop vertices: count again in the dense array
+            wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t, uint32_t w) {
+                if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
+            });
+            __syncthreads();
             const uint32_t nt = s_nt;
-            for (uint32_t t = tid; t < nt; t += kBlockThreads) {
+            for (uint32_t t = tid; t < nt; t += kRbThreads) {
                 const uint32_t w = touched[t];
                 const uint32_t c = atomicAdd(&cnt[w], 0u);
                 if (c >= jb.qA) {
                     const uint32_t s = atomicAdd(&s_k, 1u);
                     if (rows) {
-                        if (s < kSortCap) s_cand[s] = w;
                         cand_g[s] = w;
+                        atomicExch(&cnt[w], kSlotFlag | s);
                     } else {
                         if (c >= jb.n_ovf) ovf = true;
                         else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
@@ -619,57 +736,43 @@ __global__ __launch_bounds__(kBlockThreads) void k_root_build(const Job *jobs, c
                     atomicExch(&cnt[w], 0u);
                 }
             }
-        }
-        __syncthreads();
-        const uint32_t k = s_k;
-        const bool build = rows && k >= jb.pA - 1;
-        if (build && tid == 0) {
-            const unsigned long long need = (unsigned long long)k * W1;
-            const unsigned long long off = atomicAdd(pool_head, need);
-            if (off + need <= pool_cap) s_off = off;
-        }
-        __syncthreads();
-        const uint64_t off = s_off;
-        if (build && off != ~0ull) {
-            uint64_t *base = pool + off;
-            uint32_t *cand = (k <= (uint32_t)kSortCap) ? s_cand : cand_g;
-            if (k <= (uint32_t)kSortCap) block_sort_u32(s_cand, k);
             __syncthreads();
-            // mark each candidate with its row index
-            for (uint32_t s = tid; s < k; s += kBlockThreads) {
-                if (in_lds) {
-                    const uint32_t h = hash_find(s_tab, cand[s]);
-                    s_tab[h] = (s_tab[h] & 0xffffffff00000000ull) | kSlotFlag | s;
-                } else {
-                    atomicExch(&cnt[cand[s]], kSlotFlag | s);
-                }
+            k = s_k;
+            build = rows && k >= jb.pA - 1;
+            if (build && tid == 0) {
+                const unsigned long long need = (unsigned long long)k * W1;
+                const unsigned long long o = atomicAdd(pool_head, need);
+                if (o + need <= pool_cap) s_off = o;
             }
-            const uint64_t words = (uint64_t)k * W1;
-            for (uint64_t x = tid; x < words; x += kBlockThreads) base[x] = 0;
-            __threadfence();
             __syncthreads();
-            // pass 2: set bit j of row(w) for every wedge u - v_j - w with w a candidate
-            oriented_wedges(jb, u, ub, du, [&](uint32_t jj, uint32_t w) {
-                const uint32_t e = in_lds ? (uint32_t)s_tab[hash_find(s_tab, w)] : atomicAdd(&cnt[w], 0u);
-                if (e & kSlotFlag)
-                    atomicOr((unsigned long long *)&base[(uint64_t)(jj >> 6) * k + (e & ~kSlotFlag)],
-                             1ull << (jj & 63));
-            });
-            __syncthreads();
-            if (!in_lds)
-                for (uint32_t s = tid; s < k; s += kBlockThreads) atomicExch(&cnt[cand[s]], 0u);
-        } else if (rows && !in_lds) {
-            // no rows wanted (or no pool room): clear the candidates' counters
-            const uint32_t kk = min(k, sc.stride > 0 ? (uint32_t)sc.stride : 0u);
-            for (uint32_t s = tid; s < kk; s += kBlockThreads) atomicExch(&cnt[cand_g[s]], 0u);
+            off = s_off;
+            if (build && off != ~0ull) {
+                const uint64_t words = (uint64_t)k * W1;
+                for (uint64_t x = tid; x < words; x += kRbThreads) pool[off + x] = 0;
+                __threadfence();
+                __syncthreads();
+                wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t jj, uint32_t w) {
+                    const uint32_t e = atomicAdd(&cnt[w], 0u);
+                    if (e & kSlotFlag)
+                        atomicOr((unsigned long long *)&pool[off + (uint64_t)(jj >> 6) * k + (e & ~kSlotFlag)],
+                                 1ull << (jj & 63));
+                });
+                __syncthreads();
+            }
+            // reset the candidates' counters
+            if (rows)
+                for (uint32_t s = tid; s < k; s += kRbThreads) atomicExch(&cnt[cand_g[s]], 0u);
         }
         if (build && off == ~0ull && tid == 0) atomicOr(&slots[jb.slot].flags, FLAG_POOL);
         if (tid == 0) {
             out_k[item] = k;
             out_off[item] = build ? off : ~0ull;
         }
-        if (in_lds)
-            for (uint32_t x = tid; x < kHashSlots; x += kBlockThreads) s_tab[x] = 0;
+        __syncthreads();
+        for (uint32_t x = tid; x < kHashSlots; x += kRbThreads) {
+            s_key[x] = 0;
+            s_row[x] = 0;
+        }
         __syncthreads();
     }
     if (cur_job != 0xffffffffu) wave_flush(slots, jobs[cur_job].slot, acc, ovf, 0, 0);
@@ -681,7 +784,7 @@ hipError_t launch_root_build(const Job *jobs, const uint64_t *job_root_prefix, u
                              Slot *slots, hipStream_t stream)
 {
     if (total_roots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_root_build, dim3(n_blocks), dim3(kBlockThreads), 0, stream, jobs, job_root_prefix, n_jobs,
+    hipLaunchKernelGGL(k_root_build, dim3(n_blocks), dim3(kRbThreads), 0, stream, jobs, job_root_prefix, n_jobs,
                        total_roots, scratch, pool, pool_cap, counters, out_k, out_off, slots);
     return hipGetLastError();
 }
