@@ -28,7 +28,7 @@ struct Job {
     uint32_t n_u64;         // largest n with C(n, qA) < 2^64
     uint64_t deadline;      // device real-time clock tick after which the job gives up (0 = none)
     uint32_t n_u58;         // largest n with C(n, qA) < 2^58 (64 such values add up in 64 bits)
-    uint32_t pad2;
+    uint32_t n_u28;         // largest n with C(n, qA) < 2^28 (16 such values add up in 32 bits)
 };
 
 // One root that owns enumeration tasks, in schedule (cost) order.

@@ -365,7 +365,7 @@ bc_status device_clock(int device, hipStream_t st, ClockCal &out)
 
 // C(n, q) for n in [0, nmax] as exact u128; n_ovf = first n that overflows.
 void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n_ovf, uint32_t &n_u64,
-                  uint32_t &n_u58)
+                  uint32_t &n_u58, uint32_t &n_u28)
 {
     std::vector<u128> c(q + 1, 0);
     std::vector<uint8_t> ov(q + 1, 0);
@@ -386,6 +386,7 @@ void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n
         // C(n, q) does not decrease with n, so the entries below 2^64 are a prefix
         if (!ov[q] && (c[q] >> 64) == 0) n_u64 = n;
         if (!ov[q] && (c[q] >> 58) == 0) n_u58 = n;
+        if (!ov[q] && (c[q] >> 28) == 0) n_u28 = n;
     }
 }
 
@@ -541,8 +542,8 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         const HostJob &hj = jobs[j];
         const bc_graph *g = specs[hj.spec].g;
         const Side &A = g->side[hj.anchor];
-        uint32_t n_ovf = 0, n_u64 = 0, n_u58 = 0;
-        binom_column(A.max_deg, hj.qA, cols[j], n_ovf, n_u64, n_u58);
+        uint32_t n_ovf = 0, n_u64 = 0, n_u58 = 0, n_u28 = 0;
+        binom_column(A.max_deg, hj.qA, cols[j], n_ovf, n_u64, n_u58, n_u28);
         bcdev::Job &d = hjobs[j];
         memset(&d, 0, sizeof(d));
         d.ptrA = A.d_ptr;
@@ -560,6 +561,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         d.n_ovf = n_ovf;
         d.n_u64 = n_u64;
         d.n_u58 = n_u58;
+        d.n_u28 = n_u28;
         d.slot = j;
         d.deadline = 0;
         const uint64_t dl = specs[hj.spec].deadline_ns;

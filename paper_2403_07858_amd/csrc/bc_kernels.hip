@@ -19,6 +19,8 @@
 //                 pairwise sum of C(|S|, q) (leaf rule of Section III-A).
 #include "bc_device.h"
 
+#include <type_traits>
+
 namespace bcdev {
 
 constexpr uint32_t kLdsWordsPerWave = 600;    // LDS arena per wavefront (64-bit words)
@@ -827,6 +829,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t lane)
 // it was loaded for while every entry needed is below 2^64.
 struct Table {
     uint64_t *t;         // LDS
+    uint32_t *t32;       // LDS: low 32 bits of the same entries
     uint64_t *tile;      // LDS staging of one 64-row tile (64 x kTileWords words)
     uint32_t job, len;
 };
@@ -839,7 +842,11 @@ __device__ bool table_ready(Table &tb, const Job &jb, uint32_t j, uint32_t need)
     if (need > kTableLen || need > jb.n_u64 + 1 || need > jb.binom_n) return false;
     if (tb.job == j && tb.len >= need) return true;
     const uint32_t len = min(kTableLen, min(jb.binom_n, jb.n_u64 + 1));
-    for (uint32_t n = lane_id(); n < len; n += kWaveSize) tb.t[n] = (uint64_t)jb.binom[n];
+    for (uint32_t n = lane_id(); n < len; n += kWaveSize) {
+        const uint64_t x = (uint64_t)jb.binom[n];
+        tb.t[n] = x;
+        tb.t32[n] = (uint32_t)x;
+    }
     wave_sync();
     tb.job = j;
     tb.len = len;
@@ -928,6 +935,114 @@ __device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, 
     acc_flush(acc);
 }
 
+// The same sum as a product on the matrix cores.  With the rows as 0/1
+// vectors, |row_a & row_b| is entry (a, b) of R R^T, so 16 x 16 blocks of
+// intersection sizes come out of v_mfma_i32_16x16x64_i8 (one instruction per
+// 64-bit row word).  Operand layout: lane l holds row (l mod 16) of a 16-row
+// block, bits [16 (l / 16), 16 (l / 16) + 16) of each word spread to one byte
+// per bit; the A and B operands of a block are built the same way, so every
+// bit position meets its partner.  The B side is spread as 0/4 bytes and the
+// accumulator starts at the LDS byte address of the C(n, q) table, so each
+// result is already the address of its leaf value.  Result register i of
+// lane l is entry (4 (l / 16) + i, l mod 16) of the block; in a diagonal
+// block only entries above the diagonal count.  Rows past m are zero and add
+// C(0, q) = 0.
+//
+// G column blocks stay in registers while the row blocks stream by.  Every
+// table entry is below 2^28, so the 4 G <= 16 leaf values a lane takes per
+// row block add up in 32 bits.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
+__device__ __forceinline__ uint32_t lds_load_u32(uint32_t a) { return *(lds_u32 *)(uintptr_t)a; }
+
+// Bits [off, off + 16) of x (off = 16 (lane / 16)) as 16 bytes of value
+// `one` (1 or 4): nibble t of the chunk times the spreading multiplier puts
+// its bit k at bit 8k (+2 for the value 4) of dword t, with no carries.
+template <uint32_t One>
+__device__ __forceinline__ v4i spread_bits(uint64_t x, uint32_t ln)
+{
+    constexpr uint32_t mul = One == 1 ? 0x00204081u : 0x00810204u;
+    constexpr uint32_t msk = One == 1 ? 0x01010101u : 0x04040404u;
+    const uint32_t half = (ln & 32) ? (uint32_t)(x >> 32) : (uint32_t)x;
+    const uint32_t c = half >> (ln & 16);
+    v4i e;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) e[t] = (int)((((c >> (4 * t)) & 0xfu) * mul) & msk);
+    return e;
+}
+
+template <int W>
+__device__ __forceinline__ v4i mfma_block(const v4i (&ei)[W], const v4i (&ej)[W], v4i c0)
+{
+    v4i d = __builtin_amdgcn_mfma_i32_16x16x64_i8(ei[0], ej[0], c0, 0, 0, 0);
+#pragma unroll
+    for (int w = 1; w < W; ++w) d = __builtin_amdgcn_mfma_i32_16x16x64_i8(ei[w], ej[w], d, 0, 0, 0);
+    return d;
+}
+
+template <int W, int G>
+__device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, const uint32_t *t32, Acc &acc)
+{
+    const uint32_t ln = lane_id();
+    const uint32_t r16 = ln & 15;
+    const uint32_t nb = (m + 15) >> 4;
+    const int tb = (int)lds_addr(t32);   // t32[0] = C(0, q) = 0
+    const v4i c0 = {tb, tb, tb, tb};
+    bool above[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) above[i] = 4 * (ln >> 4) + (uint32_t)i < r16;
+    auto load_rows = [&](uint32_t blk_row, v4i (&e)[W], auto one) {
+        const uint32_t row = 16 * blk_row + r16;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            e[w] = spread_bits<decltype(one)::value>(row < m ? blk[(uint64_t)w * stride + row] : 0ull, ln);
+    };
+    using One = std::integral_constant<uint32_t, 1>;
+    using Four = std::integral_constant<uint32_t, 4>;
+    for (uint32_t J0 = 0; J0 < nb; J0 += G) {
+        // column blocks past the last one are zero rows and add nothing
+        v4i ej[G][W];
+#pragma unroll
+        for (int g = 0; g < G; ++g) load_rows(J0 + g, ej[g], Four{});
+        uint64_t s64 = 0;
+        // row blocks before the group: every entry is above the diagonal
+        for (uint32_t I = 0; I < J0; ++I) {
+            v4i ei[W];
+            load_rows(I, ei, One{});
+            v4i d[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) d[g] = mfma_block<W>(ei, ej[g], c0);
+            uint32_t s = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s += lds_load_u32((uint32_t)d[g][i]);
+            s64 += s;
+        }
+        // row blocks inside the group: blocks on and above the diagonal
+        const uint32_t imax = min(J0 + G, nb);
+        for (uint32_t I = J0; I < imax; ++I) {
+            v4i ei[W];
+            load_rows(I, ei, One{});
+            uint32_t s = 0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t J = J0 + g;
+                if (I > J) continue;   // wave-uniform
+                const v4i d = mfma_block<W>(ei, ej[g], c0);
+                const bool diag = I == J;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s += lds_load_u32((!diag || above[i]) ? (uint32_t)d[i] : (uint32_t)tb);
+            }
+            s64 += s;
+        }
+        acc.t += s64;
+    }
+    acc_flush(acc);
+}
+
 // Same sum through the u128 table in HBM (wide rows or entries >= 2^64).
 __device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const u128 *binom,
                              uint32_t q, uint32_t n_ovf, Acc &acc)
@@ -953,7 +1068,14 @@ __device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint3
     if (m < 2) return;
     // every popcount is at most nbits (the compacted universe)
     if (W <= kTileWords && table_ready(tb, jb, j, nbits + 1)) {
-        if (nbits <= jb.n_u58) {
+        if (nbits <= jb.n_u28) {
+            switch (W) {
+            case 1: pair_sum_mfma<1, 4>(blk, stride, m, tb.t32, acc); break;
+            case 2: pair_sum_mfma<2, 2>(blk, stride, m, tb.t32, acc); break;
+            case 3: pair_sum_mfma<3, 1>(blk, stride, m, tb.t32, acc); break;
+            default: pair_sum_mfma<4, 1>(blk, stride, m, tb.t32, acc); break;
+            }
+        } else if (nbits <= jb.n_u58) {
             switch (W) {
             case 1: pair_sum_tile<1, true>(blk, stride, m, tb.t, tb.tile, acc); break;
             case 2: pair_sum_tile<2, true>(blk, stride, m, tb.t, tb.tile, acc); break;
@@ -1325,6 +1447,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
 {
     __shared__ uint64_t lds[kWavesPerBlock][kLdsWordsPerWave];
     __shared__ uint64_t tbl[kWavesPerBlock][kTableLen];
+    __shared__ uint32_t tbl32[kWavesPerBlock][kTableLen];
     __shared__ uint64_t tiles[kWavesPerBlock][kWaveSize * kTileWords];
     const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
     const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -1338,6 +1461,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     arena.slab_used = 0;
     Table tb;
     tb.t = &tbl[wv][0];
+    tb.t32 = &tbl32[wv][0];
     tb.tile = &tiles[wv][0];
     tb.job = 0xffffffffu;
     tb.len = 0;
