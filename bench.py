@@ -112,6 +112,7 @@ def main():
             f"pair_words={st['pair_ops']} filter_words={st['filter_ops']} ms_enum={st['ms_enumerate']:.1f} "
             f"ms_cand={st['ms_candidates']:.1f} ms_rows={st['ms_rows']:.1f} ms_plan={st['ms_plan']:.1f} "
             f"cycle share " + " ".join(f"{k[4:]}={v / tot:.2f}" for k, v in cyc.items()) +
+            f" pack={st['cyc_pack'] / tot:.2f}"
             f" pairs={st['pairs']} lane_use={st['pairs'] / max(1, st['pair_slots']):.2f} "
             f"words/pair={st['pair_ops'] / max(1, st['pairs']):.2f}")
 

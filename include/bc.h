@@ -88,6 +88,8 @@ typedef struct {
                                   over wavefronts in task setup, row compaction, leaf pairs, filters */
     uint64_t pairs;            /* instrumented: leaf pairs evaluated */
     uint64_t pair_slots;       /* instrumented: lane-slots spent on them (pairs / pair_slots = lane use) */
+    uint64_t cyc_pack;         /* instrumented: the part of cyc_compact spent in tasks whose common
+                                  neighbourhood had to be bit-packed (spread over more words than it needs) */
 } bc_stats;
 
 /*

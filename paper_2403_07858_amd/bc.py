@@ -60,7 +60,8 @@ class bc_stats(ctypes.Structure):
                 ("candidate_edges", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
                 ("pair_ops", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64),
                 ("cyc_setup", ctypes.c_uint64), ("cyc_compact", ctypes.c_uint64), ("cyc_pair", ctypes.c_uint64),
-                ("cyc_filter", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("pair_slots", ctypes.c_uint64)]
+                ("cyc_filter", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("pair_slots", ctypes.c_uint64),
+                ("cyc_pack", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

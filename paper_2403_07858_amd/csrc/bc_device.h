@@ -49,6 +49,8 @@ struct Slot {
     unsigned long long pair_ops, filter_ops;
     unsigned long long cyc_setup, cyc_compact, cyc_pair, cyc_filter;   // instrumented shader-clock sums
     unsigned long long pairs, pair_slots;   // instrumented: leaf pairs, and lane-slots spent on them
+    unsigned long long cyc_pack;            // instrumented: compaction cycles of tasks that bit-pack S2
+    unsigned long long pad3;
 };
 
 enum : unsigned {

@@ -745,9 +745,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         pool_words += (uint64_t)pl.k * pl.w1;
         tasks += a.n_tasks;
         // per task: S2 and its prefix counts (2 W1), the compress table of
-        // S2's nonzero words (8 W1), then one block per DFS level
-        // 2 .. pA-2, each at most (k - 1) rows of at most W1 words
-        uint64_t need = 10ull * pl.w1 + (pA >= 4 ? (uint64_t)(pA - 3) * (pl.k - 1) * pl.w1 : 0) + 8;
+        // S2's nonzero words (8 W1), the kept-row list of the level-2 filter
+        // (k / 2 + 1), then one block per DFS level 2 .. pA-2, each at most
+        // (k - 1) rows of at most W1 words
+        uint64_t need = 10ull * pl.w1 + pl.k / 2 + 1 + (pA >= 4 ? (uint64_t)(pA - 3) * (pl.k - 1) * pl.w1 : 0) + 8;
         slab_need = std::max(slab_need, need);
     }
     const double ms_plan =
@@ -842,6 +843,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             stats->cyc_filter += sl.cyc_filter;
             stats->pairs += sl.pairs;
             stats->pair_slots += sl.pair_slots;
+            stats->cyc_pack += sl.cyc_pack;
         }
     }
     return overall;

@@ -28,6 +28,7 @@ constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of th
 constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
 constexpr uint32_t kTaskChunk = 4;            // consecutive tasks taken per queue pop
+constexpr uint32_t kFilterDepth = 4;          // 64-row chunks loaded at once by the level-2 filter
 
 
 uint32_t max_lds_words_per_wave() { return kLdsWordsPerWave; }
@@ -185,6 +186,8 @@ __global__ void k_fill_slots(Slot *slots, uint32_t n)
         slots[i].cyc_filter = 0;
         slots[i].pairs = 0;
         slots[i].pair_slots = 0;
+        slots[i].cyc_pack = 0;
+        slots[i].pad3 = 0;
     }
 }
 
@@ -1151,6 +1154,7 @@ struct Counters {
     unsigned long long pair_words, filter_words;
     unsigned long long cyc_setup, cyc_compact, cyc_pair, cyc_filter;
     unsigned long long pairs, pair_slots;
+    unsigned long long cyc_pack;
 };
 
 // Work of one pair_sum over m rows: pairs, and lane-slots the tiling spends.
@@ -1262,92 +1266,108 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     uint32_t m2 = 0;
     if (nz <= 2 && nz == W2) {
         // Common case: S2 lives in at most two words that need no packing.
-        // The two masks stay in registers and the next chunk's row words are
-        // loaded before the current chunk is filtered.
+        // The two masks stay in registers; the row words of kFilterDepth
+        // chunks are loaded together before any of them is filtered.
         const uint64_t s0 = nzt[0], s1 = (nz > 1) ? nzt[8] : 0ull;
         const uint64_t *r0 = base + (uint64_t)(uint32_t)nzt[7] * k;
         const uint64_t *r1 = base + (uint64_t)(uint32_t)((nz > 1) ? nzt[15] : nzt[7]) * k;
-        uint32_t b = i + 1 + ln;
-        uint64_t x0 = (b < k) ? r0[b] : 0ull, x1 = (nz > 1 && b < k) ? r1[b] : 0ull;
-        for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize, b += kWaveSize) {
-            const uint64_t v0 = x0 & s0, v1 = x1 & s1;
-            const uint32_t nb = b + kWaveSize;
-            x0 = (nb < k) ? r0[nb] : 0ull;
-            x1 = (nz > 1 && nb < k) ? r1[nb] : 0ull;
-            const uint32_t n = (uint32_t)(__popcll(v0) + __popcll(v1));
-            const bool keep = b < k && n >= q;
-            const uint64_t mask = __ballot(keep);
-            if (keep) {
-                const uint32_t idx = m2 + mbcnt64(mask);
-                blk2[idx] = v0;
-                if (nz > 1) blk2[(uint64_t)rem + idx] = v1;
+        for (uint32_t b0 = i + 1; b0 < k; b0 += kFilterDepth * kWaveSize) {
+            uint64_t x0[kFilterDepth], x1[kFilterDepth];
+#pragma unroll
+            for (uint32_t c = 0; c < kFilterDepth; ++c) {
+                const uint32_t b = b0 + c * kWaveSize + ln;
+                x0[c] = (b < k) ? r0[b] : 0ull;
+                x1[c] = (nz > 1 && b < k) ? r1[b] : 0ull;
             }
-            m2 += (uint32_t)__popcll(mask);
+#pragma unroll
+            for (uint32_t c = 0; c < kFilterDepth; ++c) {
+                const uint32_t b = b0 + c * kWaveSize + ln;
+                const uint64_t v0 = x0[c] & s0, v1 = x1[c] & s1;
+                const uint32_t n = (uint32_t)(__popcll(v0) + __popcll(v1));
+                const bool keep = b < k && n >= q;
+                const uint64_t mask = __ballot(keep);
+                if (keep) {
+                    const uint32_t idx = m2 + mbcnt64(mask);
+                    blk2[idx] = v0;
+                    if (nz > 1) blk2[(uint64_t)rem + idx] = v1;
+                }
+                m2 += (uint32_t)__popcll(mask);
+            }
         }
-    } else
-    for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
-        const uint32_t b = b0 + ln;
-        const bool valid = b < k;
-        const uint32_t bb = valid ? b : i;
-        uint32_t n = 0;
-        for (uint32_t e = 0; e < nz; ++e) {
-            const uint32_t w = (uint32_t)nzt[8ull * e + 7];
-            n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + bb]);
-        }
-        const bool keep = valid && n >= q;
-        const uint64_t mask = __ballot(keep);
-        if (mask && nz == W2) {
-            // S2's nonzero words are already as few as its bits need: the
-            // masked words are the compacted row (word e = S2 word e's bits)
-            const uint32_t idx = m2 + mbcnt64(mask);
+    } else {
+        // Filter first, listing the kept rows; then copy or bit-pack only
+        // those, 64 per step, so that no lane packs a row that was dropped.
+        uint32_t *kept = (uint32_t *)arena_alloc(ar, (rem + 1) / 2, cap_fail);
+        if (!kept) return;
+        for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
+            const uint32_t b = b0 + ln;
+            const bool valid = b < k;
+            const uint32_t bb = valid ? b : i;
+            uint32_t n = 0;
             for (uint32_t e = 0; e < nz; ++e) {
                 const uint32_t w = (uint32_t)nzt[8ull * e + 7];
-                const uint64_t x = nzt[8ull * e] & base[(uint64_t)w * k + bb];
-                if (keep) blk2[(uint64_t)e * rem + idx] = x;
+                n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + bb]);
             }
-        } else if (mask) {
-            // every lane walks the same entries (uniform control flow); lanes
-            // that do not keep their row write nothing
-            const uint32_t idx = m2 + mbcnt64(mask);
-            uint32_t ow = 0;
-            uint64_t cur = 0;
-            for (uint32_t e = 0; e < nz; ++e) {
-                const uint64_t *en = nzt + 8ull * e;
-                const uint64_t sw = en[0];
-                const uint32_t w = (uint32_t)en[7];
-                const uint32_t o = (uint32_t)(en[7] >> 32);   // first output bit of this word
-                uint64_t x = sw & base[(uint64_t)w * k + bb];
-#pragma unroll
-                for (int r = 0; r < 6; ++r) {
-                    const uint64_t t = x & en[1 + r];
-                    x = (x ^ t) | (t >> (1 << r));
+            const bool keep = valid && n >= q;
+            const uint64_t mask = __ballot(keep);
+            if (keep) kept[m2 + mbcnt64(mask)] = b;
+            m2 += (uint32_t)__popcll(mask);
+        }
+        wave_sync();
+        for (uint32_t c0 = 0; c0 < m2; c0 += kWaveSize) {
+            const uint32_t idx = c0 + ln;
+            const bool live = idx < m2;
+            const uint32_t bb = live ? kept[idx] : i;
+            if (nz == W2) {
+                // S2's nonzero words are already as few as its bits need: the
+                // masked words are the compacted row (word e = S2 word e's bits)
+                for (uint32_t e = 0; e < nz; ++e) {
+                    const uint32_t w = (uint32_t)nzt[8ull * e + 7];
+                    const uint64_t x = nzt[8ull * e] & base[(uint64_t)w * k + bb];
+                    if (live) blk2[(uint64_t)e * rem + idx] = x;
                 }
-                const uint32_t cnt = (uint32_t)__popcll(sw);
-                const uint32_t tw = o >> 6, sh = o & 63;
-                while (ow < tw) {
-                    if (keep) blk2[(uint64_t)ow * rem + idx] = cur;
+            } else {
+                // every lane walks the same entries (uniform control flow)
+                uint32_t ow = 0;
+                uint64_t cur = 0;
+                for (uint32_t e = 0; e < nz; ++e) {
+                    const uint64_t *en = nzt + 8ull * e;
+                    const uint64_t sw = en[0];
+                    const uint32_t w = (uint32_t)en[7];
+                    const uint32_t o = (uint32_t)(en[7] >> 32);   // first output bit of this word
+                    uint64_t x = sw & base[(uint64_t)w * k + bb];
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) {
+                        const uint64_t t = x & en[1 + r];
+                        x = (x ^ t) | (t >> (1 << r));
+                    }
+                    const uint32_t cnt = (uint32_t)__popcll(sw);
+                    const uint32_t tw = o >> 6, sh = o & 63;
+                    while (ow < tw) {
+                        if (live) blk2[(uint64_t)ow * rem + idx] = cur;
+                        cur = 0;
+                        ++ow;
+                    }
+                    cur |= x << sh;
+                    if (sh + cnt > 64) {
+                        if (live) blk2[(uint64_t)ow * rem + idx] = cur;
+                        cur = x >> (64 - sh);
+                        ++ow;
+                    }
+                }
+                while (ow < W2) {
+                    if (live) blk2[(uint64_t)ow * rem + idx] = cur;
                     cur = 0;
                     ++ow;
                 }
-                cur |= x << sh;
-                if (sh + cnt > 64) {
-                    if (keep) blk2[(uint64_t)ow * rem + idx] = cur;
-                    cur = x >> (64 - sh);
-                    ++ow;
-                }
-            }
-            while (ow < W2) {
-                if (keep) blk2[(uint64_t)ow * rem + idx] = cur;
-                cur = 0;
-                ++ow;
             }
         }
-        m2 += (uint32_t)__popcll(mask);
     }
     wave_sync();
     if (instrument) {
         const uint64_t t1 = cycles();
         ct.cyc_compact += t1 - t0;
+        if (nz != W2) ct.cyc_pack += t1 - t0;
         t0 = t1;
     }
     if (m2 < pA - 2) return;
@@ -1435,6 +1455,7 @@ __device__ void enum_flush(Slot *slots, uint32_t slot, Acc &acc, Counters &ct, b
         atomicAdd(&slots[slot].cyc_filter, ct.cyc_filter);
         atomicAdd(&slots[slot].pairs, ct.pairs);
         atomicAdd(&slots[slot].pair_slots, ct.pair_slots);
+        atomicAdd(&slots[slot].cyc_pack, ct.cyc_pack);
     }
     acc.v = 0;
     acc.ovf = false;
