@@ -996,24 +996,33 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
     bool above[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) above[i] = 4 * (ln >> 4) + (uint32_t)i < r16;
-    auto load_rows = [&](uint32_t blk_row, v4i (&e)[W], auto one) {
-        const uint32_t row = 16 * blk_row + r16;
+    // the W words of this lane's row in row block I (zero past m)
+    auto fetch = [&](uint32_t I, uint64_t (&x)[W]) {
+        const uint32_t row = 16 * I + r16;
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-            e[w] = spread_bits<decltype(one)::value>(row < m ? blk[(uint64_t)w * stride + row] : 0ull, ln);
+        for (int w = 0; w < W; ++w) x[w] = row < m ? blk[(uint64_t)w * stride + row] : 0ull;
     };
-    using One = std::integral_constant<uint32_t, 1>;
-    using Four = std::integral_constant<uint32_t, 4>;
     for (uint32_t J0 = 0; J0 < nb; J0 += G) {
         // column blocks past the last one are zero rows and add nothing
         v4i ej[G][W];
 #pragma unroll
-        for (int g = 0; g < G; ++g) load_rows(J0 + g, ej[g], Four{});
+        for (int g = 0; g < G; ++g) {
+            uint64_t x[W];
+            fetch(J0 + g, x);
+#pragma unroll
+            for (int w = 0; w < W; ++w) ej[g][w] = spread_bits<4>(x[w], ln);
+        }
+        const uint32_t imax = min(J0 + G, nb);
         uint64_t s64 = 0;
+        // row blocks I < imax; the next block's words are fetched one step ahead
+        uint64_t nx[W];
+        fetch(0, nx);
         // row blocks before the group: every entry is above the diagonal
         for (uint32_t I = 0; I < J0; ++I) {
             v4i ei[W];
-            load_rows(I, ei, One{});
+#pragma unroll
+            for (int w = 0; w < W; ++w) ei[w] = spread_bits<1>(nx[w], ln);
+            fetch(I + 1, nx);
             v4i d[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) d[g] = mfma_block<W>(ei, ej[g], c0);
@@ -1025,10 +1034,11 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
             s64 += s;
         }
         // row blocks inside the group: blocks on and above the diagonal
-        const uint32_t imax = min(J0 + G, nb);
         for (uint32_t I = J0; I < imax; ++I) {
             v4i ei[W];
-            load_rows(I, ei, One{});
+#pragma unroll
+            for (int w = 0; w < W; ++w) ei[w] = spread_bits<1>(nx[w], ln);
+            if (I + 1 < imax) fetch(I + 1, nx);
             uint32_t s = 0;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
