@@ -985,7 +985,20 @@ __device__ __forceinline__ v4i mfma_block(const v4i (&ei)[W], const v4i (&ej)[W]
     return d;
 }
 
-template <int W, int G>
+typedef __attribute__((address_space(1))) const uint64_t glb_u64;
+typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+
+// Rows in LDS or in the wave's slab: typed loads, so that row fetches from
+// the slab count only against vmcnt and the leaf-table reads' lgkmcnt waits
+// do not wait for them.
+template <bool Lds>
+__device__ __forceinline__ uint64_t row_word(const uint64_t *blk, uint64_t x)
+{
+    if constexpr (Lds) return ((lds_u64 *)blk)[x];
+    else return ((glb_u64 *)blk)[x];
+}
+
+template <int W, int G, bool Lds>
 __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, const uint32_t *t32, Acc &acc)
 {
     const uint32_t ln = lane_id();
@@ -999,8 +1012,12 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
     // the W words of this lane's row in row block I (zero past m)
     auto fetch = [&](uint32_t I, uint64_t (&x)[W]) {
         const uint32_t row = 16 * I + r16;
+        const uint32_t rr = row < m ? row : m - 1;
 #pragma unroll
-        for (int w = 0; w < W; ++w) x[w] = row < m ? blk[(uint64_t)w * stride + row] : 0ull;
+        for (int w = 0; w < W; ++w) {
+            const uint64_t v = row_word<Lds>(blk, (uint64_t)w * stride + rr);
+            x[w] = row < m ? v : 0ull;
+        }
     };
     for (uint32_t J0 = 0; J0 < nb; J0 += G) {
         // column blocks past the last one are zero rows and add nothing
@@ -1056,6 +1073,14 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
     acc_flush(acc);
 }
 
+template <int W, int G>
+__device__ __forceinline__ void pair_sum_mfma_any(const uint64_t *blk, bool in_lds, uint32_t stride, uint32_t m,
+                                                  const uint32_t *t32, Acc &acc)
+{
+    if (in_lds) pair_sum_mfma<W, G, true>(blk, stride, m, t32, acc);
+    else pair_sum_mfma<W, G, false>(blk, stride, m, t32, acc);
+}
+
 // Same sum through the u128 table in HBM (wide rows or entries >= 2^64).
 __device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, const u128 *binom,
                              uint32_t q, uint32_t n_ovf, Acc &acc)
@@ -1075,7 +1100,7 @@ __device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, u
     }
 }
 
-__device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t W, uint32_t nbits,
+__device__ void pair_sum(const uint64_t *blk, bool in_lds, uint32_t stride, uint32_t m, uint32_t W, uint32_t nbits,
                          const Job &jb, uint32_t j, Table &tb, Acc &acc)
 {
     if (m < 2) return;
@@ -1083,10 +1108,10 @@ __device__ void pair_sum(const uint64_t *blk, uint32_t stride, uint32_t m, uint3
     if (W <= kTileWords && table_ready(tb, jb, j, nbits + 1)) {
         if (nbits <= jb.n_u28) {
             switch (W) {
-            case 1: pair_sum_mfma<1, 4>(blk, stride, m, tb.t32, acc); break;
-            case 2: pair_sum_mfma<2, 2>(blk, stride, m, tb.t32, acc); break;
-            case 3: pair_sum_mfma<3, 1>(blk, stride, m, tb.t32, acc); break;
-            default: pair_sum_mfma<4, 1>(blk, stride, m, tb.t32, acc); break;
+            case 1: pair_sum_mfma_any<1, 4>(blk, in_lds, stride, m, tb.t32, acc); break;
+            case 2: pair_sum_mfma_any<2, 2>(blk, in_lds, stride, m, tb.t32, acc); break;
+            case 3: pair_sum_mfma_any<3, 1>(blk, in_lds, stride, m, tb.t32, acc); break;
+            default: pair_sum_mfma_any<4, 1>(blk, in_lds, stride, m, tb.t32, acc); break;
             }
         } else if (nbits <= jb.n_u58) {
             switch (W) {
@@ -1141,6 +1166,8 @@ struct Arena {
     uint64_t *slab;
     uint32_t lds_cap, lds_used;
     uint64_t slab_cap, slab_used;
+    // true when p was handed out from the LDS part
+    __device__ bool holds(const uint64_t *p) const { return p >= lds && p < lds + lds_cap; }
 };
 
 __device__ __forceinline__ uint64_t *arena_alloc(Arena &ar, uint64_t words, bool *fail)
@@ -1382,7 +1409,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     }
     if (m2 < pA - 2) return;
     if (pA == 4) {
-        pair_sum(blk2, rem, m2, W2, s2n, jb, jidx, tb, acc);
+        pair_sum(blk2, ar.holds(blk2), rem, m2, W2, s2n, jb, jidx, tb, acc);
         count_pairs(ct, m2, W2);
         if (instrument) ct.cyc_pair += cycles() - t0;
         return;
@@ -1437,7 +1464,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         }
         if (mc >= pA - d - 1) {
             if (d + 1 == pA - 2) {
-                pair_sum(nb, cap, mc, W2, s2n, jb, jidx, tb, acc);
+                pair_sum(nb, ar.holds(nb), cap, mc, W2, s2n, jb, jidx, tb, acc);
                 count_pairs(ct, mc, W2);
                 if (instrument) ct.cyc_pair += cycles() - t0;
             } else {
