@@ -20,15 +20,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_INT_PEAK = 256 * 4 * 16 * 2.4e9
-OPS_PER_WORD = 4   # 2 x v_and_b32 + 2 x v_bcnt_u32_b32 per 64-bit word pair
+# MI355X dense int8 matrix-core peak (no structured sparsity): 5.0 POP/s.
+MFMA_I8_PEAK = 5.0e15
+# The leaf pair sums are the int8 product R R^T of 0/1 rows: one 64-bit word
+# of both rows is 64 multiply-adds, 128 operations.
+OPS_PER_WORD_PAIR = 2 * 64
 
 # HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
 # 1 GiB device copy), valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256_PREFIX = "f91e8905877a1a3f"
-TRAFFIC_BYTES_Q44 = (932683 * 2.0 + 2915909 * 1.0) * 1024
+TRAFFIC_KERNEL_SHA256_PREFIX = "a042239c41dc0bda"
+TRAFFIC_BYTES_Q44 = (1322826 * 2.0 + 5699689 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4)]),
@@ -143,13 +145,14 @@ def main():
     roots = sum(st["roots"] for (_, _, _, st) in results[0])
     value = total_count / (ms_per_step / 1000)
 
-    # roofline of the enumeration kernel: algorithmic integer ops per launch
-    # over its mean launch time (HIP events on its stream)
+    # roofline of the enumeration kernel: algorithmic int8 matrix-core ops of
+    # its leaf pair sums per launch over its mean launch time (HIP events on
+    # its stream)
     enum_ms = {}
     for r in results:
         for (p, q, c, st) in r:
             enum_ms.setdefault((p, q), []).append(st["ms_enumerate"])
-    ops = sum(OPS_PER_WORD * (algo[k][1]["pair_ops"] + algo[k][1]["filter_ops"]) for k in algo)
+    ops = sum(OPS_PER_WORD_PAIR * algo[k][1]["pair_ops"] for k in algo)
     launch_ms = sum(sum(v) / len(v) for v in enum_ms.values())
     achieved = ops / (launch_ms / 1000) if launch_ms > 0 else 0.0
     per_query = []
@@ -161,8 +164,8 @@ def main():
         per_query.append({"p": p, "q": q, "count": str(c), "ms_total": round(mt, 3), "ms_enumerate": round(ms, 3),
                           "bicliques_per_s": c / (mt / 1000), "anchor": "UV"[st["anchor"]],
                           "tasks": st["tasks"],
-                          "enum_int_ops_per_s": OPS_PER_WORD * (st["pair_ops"] + st["filter_ops"]) / (ms / 1000)
-                          if ms > 0 else 0.0})
+                          "pair_sum_ops_per_s": OPS_PER_WORD_PAIR * st["pair_ops"] / (ms / 1000) if ms > 0 else 0.0,
+                          "leaf_pairs_per_s": st["pairs"] / (ms / 1000) if ms > 0 else 0.0})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -186,8 +189,8 @@ def main():
                    "sha256": g.manifest["sha256"]},
         "root_vertices_per_s": roots / (ms_per_step / 1000),
         "per_query": per_query,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_INT_PEAK / 1e12,
-                     "unit": "Tintop/s", "frac": achieved / VALU_INT_PEAK, "traffic": traffic_bytes(queries),
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_I8_PEAK / 1e12,
+                     "unit": "TOP/s", "dtype": "int8", "frac": achieved / MFMA_I8_PEAK, "traffic": traffic_bytes(queries),
                      "traffic_unit": "bytes per k_enumerate launch of (4,4)", "kernel": "k_enumerate"},
         "cpu_baseline": cpu,
     }

@@ -1100,18 +1100,19 @@ __device__ void pair_sum_mem(const uint64_t *blk, uint32_t stride, uint32_t m, u
     }
 }
 
-__device__ void pair_sum(const uint64_t *blk, bool in_lds, uint32_t stride, uint32_t m, uint32_t W, uint32_t nbits,
-                         const Job &jb, uint32_t j, Table &tb, Acc &acc)
+// Returns the column-group width G of the matrix-core path, 0 for the others.
+__device__ uint32_t pair_sum(const uint64_t *blk, bool in_lds, uint32_t stride, uint32_t m, uint32_t W,
+                             uint32_t nbits, const Job &jb, uint32_t j, Table &tb, Acc &acc)
 {
-    if (m < 2) return;
+    if (m < 2) return 0;
     // every popcount is at most nbits (the compacted universe)
     if (W <= kTileWords && table_ready(tb, jb, j, nbits + 1)) {
         if (nbits <= jb.n_u28) {
             switch (W) {
-            case 1: pair_sum_mfma_any<1, 4>(blk, in_lds, stride, m, tb.t32, acc); break;
-            case 2: pair_sum_mfma_any<2, 2>(blk, in_lds, stride, m, tb.t32, acc); break;
-            case 3: pair_sum_mfma_any<3, 1>(blk, in_lds, stride, m, tb.t32, acc); break;
-            default: pair_sum_mfma_any<4, 1>(blk, in_lds, stride, m, tb.t32, acc); break;
+            case 1: pair_sum_mfma_any<1, 4>(blk, in_lds, stride, m, tb.t32, acc); return 4;
+            case 2: pair_sum_mfma_any<2, 2>(blk, in_lds, stride, m, tb.t32, acc); return 2;
+            case 3: pair_sum_mfma_any<3, 1>(blk, in_lds, stride, m, tb.t32, acc); return 1;
+            default: pair_sum_mfma_any<4, 1>(blk, in_lds, stride, m, tb.t32, acc); return 1;
             }
         } else if (nbits <= jb.n_u58) {
             switch (W) {
@@ -1131,6 +1132,7 @@ __device__ void pair_sum(const uint64_t *blk, bool in_lds, uint32_t stride, uint
     } else {
         pair_sum_mem(blk, stride, m, W, jb.binom, jb.qA, jb.n_ovf, acc);
     }
+    return 0;
 }
 
 // Children of row a: rows b > a whose AND with row a keeps >= q bits, written
@@ -1194,12 +1196,24 @@ struct Counters {
     unsigned long long cyc_pack;
 };
 
-// Work of one pair_sum over m rows: pairs, and lane-slots the tiling spends.
-__device__ __forceinline__ void count_pairs(Counters &ct, uint32_t m, uint32_t W)
+// Work of one pair_sum over m rows: pairs, and pair positions (lane-slots)
+// the chosen path spends: 16 x 16 blocks of G column blocks on the matrix
+// cores (G > 0), else 64-row tiles with the folded diagonal tile.
+__device__ __forceinline__ void count_pairs(Counters &ct, uint32_t m, uint32_t W, uint32_t G)
 {
     const unsigned long long pr = (unsigned long long)m * (m - 1) / 2;
     ct.pairs += pr;
     ct.pair_words += pr * W;
+    if (G) {
+        const uint32_t nb = (m + 15) / 16;
+        unsigned long long blocks = 0;
+        for (uint32_t J0 = 0; J0 < nb; J0 += G) {
+            blocks += (unsigned long long)J0 * G;
+            for (uint32_t I = J0; I < min(J0 + G, nb); ++I) blocks += J0 + G - I;
+        }
+        ct.pair_slots += blocks * 256;
+        return;
+    }
     for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize)   // full tiles, then the folded diagonal tile
         ct.pair_slots += (unsigned long long)(b0 / kWaveSize) * kWaveSize * kWaveSize +
                          (unsigned long long)(min((uint32_t)kWaveSize, m - b0) / 2) * kWaveSize;
@@ -1217,7 +1231,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - jb.ptrA[u]);
     const uint32_t W1 = (du + 63) >> 6;
     const uint32_t k = rt.k;
-    const uint64_t *base = pool + rt.pool_off;
+    glb_u64 *base = (glb_u64 *)(pool + rt.pool_off);   // the root's rows (global: typed loads)
     const uint32_t q = jb.qA, pA = jb.pA;
     uint64_t t0 = instrument ? cycles() : 0;
 
@@ -1278,7 +1292,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         nz += (uint32_t)__popcll(nzmask);
     }
     wave_sync();
-    ct.filter_words += (unsigned long long)rem * nz;
+    if (instrument) ct.filter_words += (unsigned long long)rem * nz;
 
     if (pA == 3) {
         // Leaves {u, c_i, c_b}: sum of C(|S2 n row_b|, q).
@@ -1306,8 +1320,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         // The two masks stay in registers; the row words of kFilterDepth
         // chunks are loaded together before any of them is filtered.
         const uint64_t s0 = nzt[0], s1 = (nz > 1) ? nzt[8] : 0ull;
-        const uint64_t *r0 = base + (uint64_t)(uint32_t)nzt[7] * k;
-        const uint64_t *r1 = base + (uint64_t)(uint32_t)((nz > 1) ? nzt[15] : nzt[7]) * k;
+        glb_u64 *r0 = base + (uint64_t)(uint32_t)nzt[7] * k;
+        glb_u64 *r1 = base + (uint64_t)(uint32_t)((nz > 1) ? nzt[15] : nzt[7]) * k;
         for (uint32_t b0 = i + 1; b0 < k; b0 += kFilterDepth * kWaveSize) {
             uint64_t x0[kFilterDepth], x1[kFilterDepth];
 #pragma unroll
@@ -1409,8 +1423,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     }
     if (m2 < pA - 2) return;
     if (pA == 4) {
-        pair_sum(blk2, ar.holds(blk2), rem, m2, W2, s2n, jb, jidx, tb, acc);
-        count_pairs(ct, m2, W2);
+        const uint32_t G = pair_sum(blk2, ar.holds(blk2), rem, m2, W2, s2n, jb, jidx, tb, acc);
+        if (instrument) count_pairs(ct, m2, W2, G);
         if (instrument) ct.cyc_pair += cycles() - t0;
         return;
     }
@@ -1456,7 +1470,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         if (!nb) return;
         if (instrument) t0 = cycles();
         const uint32_t mc = filter_children(blk, stride, m, a, W2, q, nb, cap);
-        ct.filter_words += (unsigned long long)cap * W2;
+        if (instrument) ct.filter_words += (unsigned long long)cap * W2;
         if (instrument) {
             const uint64_t t1 = cycles();
             ct.cyc_filter += t1 - t0;
@@ -1464,8 +1478,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         }
         if (mc >= pA - d - 1) {
             if (d + 1 == pA - 2) {
-                pair_sum(nb, ar.holds(nb), cap, mc, W2, s2n, jb, jidx, tb, acc);
-                count_pairs(ct, mc, W2);
+                const uint32_t G = pair_sum(nb, ar.holds(nb), cap, mc, W2, s2n, jb, jidx, tb, acc);
+                if (instrument) count_pairs(ct, mc, W2, G);
                 if (instrument) ct.cyc_pair += cycles() - t0;
             } else {
                 ++d;
