@@ -1,14 +1,16 @@
 // HIP kernels of the (p,q)-biclique counter for CDNA4 (gfx950, wave64).
 //
 // The search follows Algorithm 1 (GBC) restated for this hardware:
-//   k_cand_count  per root u: oriented 2-hop candidates w > u sharing at least
+//   k_root_build  per root u: oriented 2-hop candidates w > u sharing at least
 //                 qA neighbours with u (N_2^q(u) of Section II-A with the
-//                 vertex-priority orientation of Section III-B).  For pA == 2
-//                 the leaves C(|N(u) n N(w)|, qA) are summed right here.
-//   k_rows_build  per root u: one bitmap row per candidate w over the local
-//                 ids of N(u) (bit j set when the j-th neighbour of u is also
-//                 a neighbour of w) -- a truncated bitmap in the spirit of the
+//                 vertex-priority orientation of Section III-B), and one
+//                 bitmap row per candidate over the neighbours of u (column
+//                 d(u) - 1 - j set when the j-th neighbour of u is also a
+//                 neighbour of w) -- a truncated bitmap in the spirit of the
 //                 HTB of Section V-A, dense over the root's own neighbourhood.
+//                 For pA == 2 the leaves C(|N(u) n N(w)|, qA) are summed
+//                 right here.  k_cand_count + k_rows_build do the same in two
+//                 kernels with global counters (fallback).
 //   k_enumerate   persistent wavefronts pop (root, second vertex) tasks -- the
 //                 edge-oriented pre-runtime split of Section V-C -- from one
 //                 device queue (runtime balancing, Section V-C), compact the
@@ -16,7 +18,8 @@
 //                 the hybrid DFS-BFS of Section IV: DFS over levels, all
 //                 siblings of a node intersected at once by the 64 lanes
 //                 (AND + popcount), and the last two levels fused into one
-//                 pairwise sum of C(|S|, q) (leaf rule of Section III-A).
+//                 pairwise sum of C(|S|, q) (leaf rule of Section III-A) whose
+//                 intersection sizes come from the matrix cores.
 #include "bc_device.h"
 
 #include <type_traits>
@@ -242,9 +245,12 @@ hipError_t launch_degree_sum(const Job *jobs, const uint32_t *job_ids, uint32_t 
 
 // ---------------------------------------------------------------------------
 // Wedge scan shared by the two-kernel per-root path: for every neighbour v_j
-// of u (j = local id) and every w in N(v_j) with w > u, call f(j, w).  Waves
-// take the j's round robin; lanes stride over the oriented part of N(v_j),
-// which starts right after u (its position within N(v_j) is stored per edge).
+// of u and every w in N(v_j) with w > u, call f(c, w), where c = d(u) - 1 - j
+// is v_j's column (bit position) in the root's rows: the highest-ranked
+// neighbours, which most candidates share, take the first word, so common
+// neighbourhoods tend to need no bit-packing.  Waves take the j's round
+// robin; lanes stride over the oriented part of N(v_j), which starts right
+// after u (its position within N(v_j) is stored per edge).
 template <typename F>
 __device__ __forceinline__ void oriented_wedges(const Job &jb, uint32_t u, uint64_t ub, uint32_t du, F f)
 {
@@ -252,11 +258,11 @@ __device__ __forceinline__ void oriented_wedges(const Job &jb, uint32_t u, uint6
     for (uint32_t j = wv; j < du; j += kWavesPerBlock) {
         const uint32_t v = jb.adjA[ub + j];
         const uint64_t s = jb.ptrB[v] + jb.rposA[ub + j] + 1, ve = jb.ptrB[v + 1];
-        for (uint64_t x = s + ln; x < ve; x += kWaveSize) f(j, jb.adjB[x]);
+        for (uint64_t x = s + ln; x < ve; x += kWaveSize) f(du - 1 - j, jb.adjB[x]);
     }
 }
 
-// The same wedges spread evenly over the NW waves of a block.  The
+// The same wedges (and columns) spread evenly over the NW waves of a block.  The
 // neighbours of u are taken 64 at a time, one per lane; a wave scan lays the
 // 64 oriented parts of their rows end to end, and the waves take 64-element
 // windows of that concatenation round robin, two windows per step.  Each lane
@@ -292,8 +298,8 @@ __device__ __forceinline__ void wedges_flat(const Job &jb, uint64_t ub, uint32_t
             uint32_t wa = 0, wb = 0;
             if (xa < total) wa = jb.adjB[pa];
             if (xb < total) wb = jb.adjB[pb];
-            if (xa < total) f(j0 + la, wa);
-            if (xb < total) f(j0 + lb, wb);
+            if (xa < total) f(du - 1 - (j0 + la), wa);
+            if (xb < total) f(du - 1 - (j0 + lb), wb);
         }
     }
 }
@@ -511,8 +517,9 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
 //
 // The 2-hop vertices of u live in an LDS open-addressing table (key w + 1,
 // linear probing).  When u has at most 64 neighbours (one row word), the
-// table entry accumulates w's row itself -- bit j set for the wedge u - v_j -
-// w -- so one wedge pass yields both |N(u) n N(w)| (the popcount) and the row.
+// table entry accumulates w's row itself -- v_j's column set for the wedge
+// u - v_j - w -- so one wedge pass yields both |N(u) n N(w)| (the popcount)
+// and the row.
 // Wider roots count in the first pass, index their candidates, and set the
 // row bits in a second pass into LDS (or the pool when the rows do not fit).
 // Roots whose 2-hop set overflows the table fall back to the per-block dense
@@ -703,7 +710,7 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
                         for (uint64_t x = tid; x < words; x += kRbThreads) pool[off + x] = 0;
                     __threadfence();
                     __syncthreads();
-                    // pass 2: set bit j of row(w) for every wedge u - v_j - w with w a candidate
+                    // pass 2: set v_j's column bit of row(w) for every wedge u - v_j - w with w a candidate
                     wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t jj, uint32_t w) {
                         const uint32_t m = s_map[hash_find(s_key, w)];
                         if (m != kNoRow) {
