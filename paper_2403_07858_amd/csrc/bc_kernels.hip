@@ -1242,63 +1242,93 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     const uint32_t q = jb.qA, pA = jb.pA;
     uint64_t t0 = instrument ? cycles() : 0;
 
-    // S2 = row i (common neighbours of u and c_i) and its word prefix counts.
-    uint64_t *s2 = arena_alloc(ar, 2ull * W1, cap_fail);
-    if (!s2) return;
-    uint64_t *pre = s2 + W1;
-    for (uint32_t w = ln; w < W1; w += kWaveSize) s2[w] = base[(uint64_t)w * k + i];
-    wave_sync();
-    uint32_t running = 0;
-    for (uint32_t w0 = 0; w0 < W1; w0 += kWaveSize) {
-        const uint32_t w = w0 + ln;
-        const uint32_t c = (w < W1) ? (uint32_t)__popcll(s2[w]) : 0u;
-        const uint32_t incl = wave_inclusive_scan(c);
-        if (w < W1) pre[w] = running + incl - c;
-        running += bcast32(incl, kWaveSize - 1);
-    }
-    wave_sync();
-    const uint32_t s2n = running;
-    const uint32_t W2 = (s2n + 63) >> 6;
     const uint32_t rem = k - i - 1;
-    if (instrument) {
-        const uint64_t t1 = cycles();
-        ct.cyc_setup += t1 - t0;
-        t0 = t1;
-    }
-
-    // The nonzero words of S2, each with the six masks of the compress
-    // operation (Hacker's Delight, "compress" / parallel bit extract) that
-    // packs the bits selected by that word to the right: entry e holds
-    // {s2 word, mv0..mv5, w | pre << 32}.  Empty words of S2 are skipped.
-    uint64_t *nzt = arena_alloc(ar, 8ull * W1, cap_fail);
-    if (!nzt) return;
-    uint32_t nz = 0;
-    for (uint32_t w0 = 0; w0 < W1; w0 += kWaveSize) {
-        const uint32_t w = w0 + ln;
-        const uint64_t sw = (w < W1) ? s2[w] : 0ull;
-        const uint64_t nzmask = __ballot(sw != 0);
-        if (sw != 0) {
-            uint64_t *e = nzt + 8ull * (nz + mbcnt64(nzmask));
-            e[0] = sw;
-            uint64_t m = sw, mk = ~sw << 1;
-#pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                uint64_t mp = mk ^ (mk << 1);
-                mp ^= mp << 2;
-                mp ^= mp << 4;
-                mp ^= mp << 8;
-                mp ^= mp << 16;
-                mp ^= mp << 32;
-                const uint64_t mv = mp & m;
-                e[1 + r] = mv;
-                m = (m ^ mv) | (mv >> (1 << r));
-                mk &= ~mp;
-            }
-            e[7] = (uint64_t)w | ((uint64_t)pre[w] << 32);
+    // S2 = row i (common neighbours of u and c_i).  Its first two nonzero
+    // words (s0, s1, at word indices w0, w1) stay in scalar registers; wider
+    // roots also get the table of all nonzero words.
+    uint32_t s2n, nz;
+    uint64_t s0 = 0, s1 = 0;
+    uint32_t w0 = 0, w1 = 0;
+    uint64_t *nzt = nullptr;
+    if (W1 == 1) {
+        // one-word root: nothing to scan or tabulate
+        const uint64_t x = base[i];
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+        s0 = ((uint64_t)hi << 32) | lo;
+        s2n = (uint32_t)__popcll(s0);
+        nz = s0 != 0 ? 1u : 0u;
+        if (instrument) {
+            const uint64_t t1 = cycles();
+            ct.cyc_setup += t1 - t0;
+            t0 = t1;
         }
-        nz += (uint32_t)__popcll(nzmask);
+    } else {
+        // S2 and its word prefix counts
+        uint64_t *s2 = arena_alloc(ar, 2ull * W1, cap_fail);
+        if (!s2) return;
+        uint64_t *pre = s2 + W1;
+        for (uint32_t w = ln; w < W1; w += kWaveSize) s2[w] = base[(uint64_t)w * k + i];
+        wave_sync();
+        uint32_t running = 0;
+        for (uint32_t x0 = 0; x0 < W1; x0 += kWaveSize) {
+            const uint32_t w = x0 + ln;
+            const uint32_t c = (w < W1) ? (uint32_t)__popcll(s2[w]) : 0u;
+            const uint32_t incl = wave_inclusive_scan(c);
+            if (w < W1) pre[w] = running + incl - c;
+            running += bcast32(incl, kWaveSize - 1);
+        }
+        wave_sync();
+        s2n = running;
+        if (instrument) {
+            const uint64_t t1 = cycles();
+            ct.cyc_setup += t1 - t0;
+            t0 = t1;
+        }
+
+        // The nonzero words of S2, each with the six masks of the compress
+        // operation (Hacker's Delight, "compress" / parallel bit extract) that
+        // packs the bits selected by that word to the right: entry e holds
+        // {s2 word, mv0..mv5, w | pre << 32}.  Empty words of S2 are skipped.
+        nzt = arena_alloc(ar, 8ull * W1, cap_fail);
+        if (!nzt) return;
+        nz = 0;
+        for (uint32_t x0 = 0; x0 < W1; x0 += kWaveSize) {
+            const uint32_t w = x0 + ln;
+            const uint64_t sw = (w < W1) ? s2[w] : 0ull;
+            const uint64_t nzmask = __ballot(sw != 0);
+            if (sw != 0) {
+                uint64_t *e = nzt + 8ull * (nz + mbcnt64(nzmask));
+                e[0] = sw;
+                uint64_t m = sw, mk = ~sw << 1;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    uint64_t mp = mk ^ (mk << 1);
+                    mp ^= mp << 2;
+                    mp ^= mp << 4;
+                    mp ^= mp << 8;
+                    mp ^= mp << 16;
+                    mp ^= mp << 32;
+                    const uint64_t mv = mp & m;
+                    e[1 + r] = mv;
+                    m = (m ^ mv) | (mv >> (1 << r));
+                    mk &= ~mp;
+                }
+                e[7] = (uint64_t)w | ((uint64_t)pre[w] << 32);
+            }
+            nz += (uint32_t)__popcll(nzmask);
+        }
+        wave_sync();
+        if (nz > 0) {
+            s0 = nzt[0];
+            w0 = (uint32_t)nzt[7];
+        }
+        if (nz > 1) {
+            s1 = nzt[8];
+            w1 = (uint32_t)nzt[15];
+        }
     }
-    wave_sync();
+    const uint32_t W2 = (s2n + 63) >> 6;
     if (instrument) ct.filter_words += (unsigned long long)rem * nz;
 
     if (pA == 3) {
@@ -1307,9 +1337,14 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
             const uint32_t b = b0 + ln;
             if (b < k) {
                 uint32_t n = 0;
-                for (uint32_t e = 0; e < nz; ++e) {
-                    const uint32_t w = (uint32_t)nzt[8ull * e + 7];
-                    n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + b]);
+                if (nz <= 2) {
+                    if (nz > 0) n += __popcll(s0 & base[(uint64_t)w0 * k + b]);
+                    if (nz > 1) n += __popcll(s1 & base[(uint64_t)w1 * k + b]);
+                } else {
+                    for (uint32_t e = 0; e < nz; ++e) {
+                        const uint32_t w = (uint32_t)nzt[8ull * e + 7];
+                        n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + b]);
+                    }
                 }
                 if (n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
             }
@@ -1326,9 +1361,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         // Common case: S2 lives in at most two words that need no packing.
         // The two masks stay in registers; the row words of kFilterDepth
         // chunks are loaded together before any of them is filtered.
-        const uint64_t s0 = nzt[0], s1 = (nz > 1) ? nzt[8] : 0ull;
-        glb_u64 *r0 = base + (uint64_t)(uint32_t)nzt[7] * k;
-        glb_u64 *r1 = base + (uint64_t)(uint32_t)((nz > 1) ? nzt[15] : nzt[7]) * k;
+        glb_u64 *r0 = base + (uint64_t)w0 * k;
+        glb_u64 *r1 = base + (uint64_t)(nz > 1 ? w1 : w0) * k;
         for (uint32_t b0 = i + 1; b0 < k; b0 += kFilterDepth * kWaveSize) {
             uint64_t x0[kFilterDepth], x1[kFilterDepth];
 #pragma unroll
