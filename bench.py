@@ -114,7 +114,7 @@ def main():
             f"pair_words={st['pair_ops']} filter_words={st['filter_ops']} ms_enum={st['ms_enumerate']:.1f} "
             f"ms_cand={st['ms_candidates']:.1f} ms_rows={st['ms_rows']:.1f} ms_plan={st['ms_plan']:.1f} "
             f"cycle share " + " ".join(f"{k[4:]}={v / tot:.2f}" for k, v in cyc.items()) +
-            f" pack={st['cyc_pack'] / tot:.2f}"
+            f" pack={st['cyc_pack'] / tot:.2f} task_cycles={tot:.4g}"
             f" pairs={st['pairs']} lane_use={st['pairs'] / max(1, st['pair_slots']):.2f} "
             f"words/pair={st['pair_ops'] / max(1, st['pairs']):.2f}")
 
@@ -281,8 +281,19 @@ def run_batch(args):
     _log(f"[batch] built {len(graphs)} graphs in {time.time() - t0:.1f}s")
     opt = {"stream": stream, "timeout_ms": args.timeout_ms}
 
-    # warmup: the batched path once
-    vals, st = bc.bc_count_batch(graphs, ps, qs, **opt)
+    # warmup: the batched path once, instrumented
+    vals, st, agg = bc.bc_count_batch(graphs, ps, qs, with_stats=True, instrument=True, **opt)
+    cyc = {k: agg[k] for k in ("cyc_setup", "cyc_compact", "cyc_pair", "cyc_filter")}
+    tot = sum(cyc.values()) or 1
+    _log(f"[batch] instrumented pass: ms_cand={agg['ms_candidates']:.1f} ms_plan={agg['ms_plan']:.1f} "
+         f"ms_rows={agg['ms_rows']:.1f} ms_enum={agg['ms_enumerate']:.1f} ms_total={agg['ms_total']:.1f} "
+         f"roots={agg['roots']} tasks={agg['tasks']} pairs={agg['pairs']} "
+         f"words/pair={agg['pair_ops'] / max(1, agg['pairs']):.2f} "
+         f"lane_use={agg['pairs'] / max(1, agg['pair_slots']):.2f} task_cycles={tot:.4g} cycle share " +
+         " ".join(f"{k[4:]}={v / tot:.2f}" for k, v in cyc.items()))
+    vals, st, agg = bc.bc_count_batch(graphs, ps, qs, with_stats=True, **opt)
+    _log(f"[batch] timed-mode pass: ms_cand={agg['ms_candidates']:.1f} ms_plan={agg['ms_plan']:.1f} "
+         f"ms_rows={agg['ms_rows']:.1f} ms_enum={agg['ms_enumerate']:.1f} ms_total={agg['ms_total']:.1f}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

@@ -145,10 +145,12 @@ bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, int32_t anch
  * bc_count_batch -- n independent counts (graphs[i], p[i], q[i]) in one set
  * of persistent launches sharing one task queue.  out[i] and item_status[i]
  * receive each result; the call itself fails only on argument or device
- * errors.  Every out[i] equals what bc_count would return.
+ * errors.  Every out[i] equals what bc_count would return.  st (nullable)
+ * receives the timings of the whole call and work counters summed over all
+ * items (anchor: that of the first item).
  */
 bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q,
-                         size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status);
+                         size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st);
 
 /* Human-readable name of a status code (static storage). */
 const char *bc_status_string(bc_status s);

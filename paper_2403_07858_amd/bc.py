@@ -82,7 +82,7 @@ def _load():
         "bc_ranks": ([P, I32, P], I32),
         "bc_count": ([P, U32, U32, P, P, P], I32),
         "bc_count_roots": ([P, U32, U32, I32, U64, U64, P, P, P], I32),
-        "bc_count_batch": ([P, P, P, SZ, P, P, P], I32),
+        "bc_count_batch": ([P, P, P, SZ, P, P, P, P], I32),
         "bc_status_string": ([I32], ctypes.c_char_p),
         "bc_last_error": ([], ctypes.c_char_p),
     }
@@ -228,8 +228,9 @@ def bc_count_roots(g: Graph, p: int, q: int, anchor: int, rank_lo: int, rank_hi:
     return (out.value, st.as_dict()) if with_stats else out.value
 
 
-def bc_count_batch(graphs, ps, qs, **opt):
-    """Counts for many (graph, p, q) in one set of launches: (values, statuses)."""
+def bc_count_batch(graphs, ps, qs, with_stats=False, **opt):
+    """Counts for many (graph, p, q) in one set of launches: (values, statuses),
+    plus the aggregate stats when with_stats."""
     n = len(graphs)
     hs = (ctypes.c_void_p * max(1, n))(*[g.handle for g in graphs])
     pa = np.ascontiguousarray(ps, dtype=np.uint32)
@@ -237,10 +238,13 @@ def bc_count_batch(graphs, ps, qs, **opt):
     out = (bc_u128 * max(1, n))()
     st = np.zeros(max(1, n), dtype=np.int32)
     o = make_opts(**opt)
-    s = _lib.bc_count_batch(hs, pa.ctypes.data, qa.ctypes.data, n, ctypes.byref(o), out, st.ctypes.data)
+    agg = bc_stats()
+    s = _lib.bc_count_batch(hs, pa.ctypes.data, qa.ctypes.data, n, ctypes.byref(o), out, st.ctypes.data,
+                            ctypes.byref(agg))
     if s != BC_OK:
         raise BCError(s, "bc_count_batch")
-    return [out[i].value for i in range(n)], [int(x) for x in st[:n]]
+    res = ([out[i].value for i in range(n)], [int(x) for x in st[:n]])
+    return res + (agg.as_dict(),) if with_stats else res
 
 
 # ---------------------------------------------------------------------------

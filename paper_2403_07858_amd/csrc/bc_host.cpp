@@ -748,7 +748,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         // S2's nonzero words (8 W1), the kept-row list of the level-2 filter
         // (k / 2 + 1), then one block per DFS level 2 .. pA-2, each at most
         // (k - 1) rows of at most W1 words
-        uint64_t need = 10ull * pl.w1 + pl.k / 2 + 1 + (pA >= 4 ? (uint64_t)(pA - 3) * (pl.k - 1) * pl.w1 : 0) + 8;
+        // (p_A >= 5: plus the pair rows of one small node's three-level sum,
+        // at most 96*95/2 rows of at most 4 words and their u32 indices)
+        uint64_t need = 10ull * pl.w1 + pl.k / 2 + 1 + (pA >= 5 ? 4560ull * 4 + 2281 : 0) +
+                        (pA >= 4 ? (uint64_t)(pA - 3) * (pl.k - 1) * pl.w1 : 0) + 8;
         slab_need = std::max(slab_need, need);
     }
     const double ms_plan =
@@ -901,9 +904,10 @@ extern "C" bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, i
 }
 
 extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
-                                    const bc_opts *opts, bc_u128 *out, bc_status *item_status)
+                                    const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st)
 {
     g_last_error.clear();
+    if (st) memset(st, 0, sizeof(*st));
     if (n == 0) return BC_OK;
     if (!graphs || !p || !q || !out || !item_status) return set_error(BC_E_INVALID_ARG, "bc_count_batch: NULL argument");
     if (bc_status s = check_opts(opts)) return s;
@@ -923,7 +927,8 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
     }
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
-    bc_status s = run_jobs(sp, opts, res, ist, nullptr);
+    if (sp.empty()) return BC_OK;
+    bc_status s = run_jobs(sp, opts, res, ist, st);
     if (s != BC_OK && s != BC_E_DEVICE) return s;
     for (size_t t = 0; t < idx.size(); ++t) {
         item_status[idx[t]] = ist[t];

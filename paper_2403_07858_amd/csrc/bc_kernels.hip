@@ -32,6 +32,7 @@ constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
 constexpr uint32_t kTaskChunk = 4;            // consecutive tasks taken per queue pop
 constexpr uint32_t kFilterDepth = 4;          // 64-row chunks loaded at once by the level-2 filter
+constexpr uint32_t kTripleRows = 96;          // nodes up to this many rows finish their last three levels at once
 
 
 uint32_t max_lds_words_per_wave() { return kLdsWordsPerWave; }
@@ -1142,6 +1143,94 @@ __device__ uint32_t pair_sum(const uint64_t *blk, bool in_lds, uint32_t stride, 
     return 0;
 }
 
+// The last three levels of a small node at once: over the node's rows
+// r_0 .. r_{m-1} (W words each), sum over a < b < c of C(|r_a & r_b & r_c|, q).
+// This equals what the children of the node and their leaf sums add up to
+// (a child a keeps b when |r_a & r_b| >= q; dropped pairs only had zero
+// leaves).  Pair rows p_ab = r_a & r_b with at least q bits are listed in
+// order of b (rows of P, b in Pb); then each 16-pair block of P meets the
+// 16-row blocks of the node's rows c on the matrix cores exactly like
+// pair_sum_mfma, keeping entries with c > b.  One sweep replaces m leaf sums
+// over short lists.  P holds pcap pair rows (W words each, stride pcap)
+// followed by pcap u32 values of b.
+template <int W, bool Lds>
+__device__ void triple_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t q, uint64_t *P,
+                                uint32_t pcap, const uint32_t *t32, Acc &acc, unsigned long long *pairs)
+{
+    const uint32_t ln = lane_id();
+    const uint32_t r16 = ln & 15;
+    uint32_t *Pb = (uint32_t *)(P + (uint64_t)W * pcap);
+    // 1. pair rows, b-major
+    uint32_t np = 0;
+    unsigned long long useful = 0;
+    for (uint32_t b = 1; b < m; ++b) {
+        uint64_t rb[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) rb[w] = row_word<Lds>(blk, (uint64_t)w * stride + b);
+        for (uint32_t a0 = 0; a0 < b; a0 += kWaveSize) {
+            const uint32_t a = a0 + ln;
+            const bool valid = a < b;
+            const uint32_t aa = valid ? a : 0u;
+            uint64_t v[W];
+            uint32_t n = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                v[w] = row_word<Lds>(blk, (uint64_t)w * stride + aa) & rb[w];
+                n += (uint32_t)__popcll(v[w]);
+            }
+            const bool keep = valid && n >= q;
+            const uint64_t mask = __ballot(keep);
+            if (keep) {
+                const uint32_t idx = np + mbcnt64(mask);
+#pragma unroll
+                for (int w = 0; w < W; ++w) P[(uint64_t)w * pcap + idx] = v[w];
+                Pb[idx] = b;
+            }
+            const uint32_t kept = (uint32_t)__popcll(mask);
+            np += kept;
+            useful += (unsigned long long)kept * (m - 1 - b);
+        }
+    }
+    *pairs += useful;
+    wave_sync();
+    // 2. pair-row blocks against row blocks c > b
+    const uint32_t nbc = (m + 15) >> 4;
+    const int tb = (int)lds_addr(t32);   // t32[0] = C(0, q) = 0
+    const v4i c0 = {tb, tb, tb, tb};
+    for (uint32_t i0 = 0; i0 < np; i0 += 16) {
+        const uint32_t pr = i0 + r16;
+        const bool pv = pr < np;
+        const uint32_t prr = pv ? pr : np - 1;
+        v4i ea[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) ea[w] = spread_bits<1>(pv ? P[(uint64_t)w * pcap + prr] : 0ull, ln);
+        const uint32_t bmine = pv ? Pb[prr] : 0xffffffffu;
+        uint32_t brow[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) brow[i] = (uint32_t)__shfl((int)bmine, (int)(4 * (ln >> 4) + i));
+        const uint32_t bmin = __builtin_amdgcn_readfirstlane(Pb[i0]);   // b-major: the block's smallest b
+        uint64_t s64 = 0;
+        for (uint32_t J = (bmin + 1) >> 4; J < nbc; ++J) {
+            const uint32_t c = 16 * J + r16;
+            const uint32_t cc = c < m ? c : m - 1;
+            v4i eb[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t x = row_word<Lds>(blk, (uint64_t)w * stride + cc);
+                eb[w] = spread_bits<4>(c < m ? x : 0ull, ln);
+            }
+            const v4i dd = mfma_block<W>(ea, eb, c0);
+            uint32_t s = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += lds_load_u32(c > brow[i] ? (uint32_t)dd[i] : (uint32_t)tb);
+            s64 += s;
+        }
+        acc.t += s64;
+    }
+    acc_flush(acc);
+    wave_sync();
+}
+
 // Children of row a: rows b > a whose AND with row a keeps >= q bits, written
 // (ANDed) into nblk (stride nstride) in order.  Returns their number.
 __device__ uint32_t filter_children(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t a, uint32_t W,
@@ -1493,7 +1582,46 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         const uint64_t *blk = dec_ptr(stack[4 * d + 0]);
         const uint32_t stride = (uint32_t)stack[4 * d + 1];
         const uint32_t m = (uint32_t)(stack[4 * d + 1] >> 32);
-        const uint32_t a = (uint32_t)stack[4 * d + 2];
+        uint32_t a = (uint32_t)stack[4 * d + 2];
+        // a small node two levels above the leaves: its last three levels in
+        // one matrix-core sweep, then the node is done
+        if (d + 3 == pA && a == 0 && m >= 3 && m <= kTripleRows && W2 <= kTileWords && s2n <= jb.n_u28 &&
+            table_ready(tb, jb, jidx, s2n + 1)) {
+            const uint32_t pcap = m * (m - 1) / 2;
+            const uint64_t mark = (uint64_t)ar.lds_used | (ar.slab_used << 32);
+            uint64_t *P = arena_alloc(ar, (uint64_t)pcap * W2 + (pcap + 1) / 2, cap_fail);
+            if (!P) return;
+            if (instrument) t0 = cycles();
+            unsigned long long tp = 0;
+            const bool lds_blk = ar.holds(blk);
+            switch (W2) {
+            case 1:
+                if (lds_blk) triple_sum_mfma<1, true>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                else triple_sum_mfma<1, false>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                break;
+            case 2:
+                if (lds_blk) triple_sum_mfma<2, true>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                else triple_sum_mfma<2, false>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                break;
+            case 3:
+                if (lds_blk) triple_sum_mfma<3, true>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                else triple_sum_mfma<3, false>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                break;
+            default:
+                if (lds_blk) triple_sum_mfma<4, true>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                else triple_sum_mfma<4, false>(blk, stride, m, q, P, pcap, tb.t32, acc, &tp);
+                break;
+            }
+            if (instrument) {
+                ct.pairs += tp;
+                ct.pair_words += tp * W2;
+                ct.filter_words += (unsigned long long)pcap * W2;
+                ct.cyc_pair += cycles() - t0;
+            }
+            ar.lds_used = (uint32_t)(mark & 0xffffffffu);
+            ar.slab_used = mark >> 32;
+            a = m;   // exhausted: pop below
+        }
         // row a needs pA - d - 1 more rows after it
         if ((int64_t)a > (int64_t)m - (int64_t)pA + (int64_t)d) {
             if (d == 2) break;
