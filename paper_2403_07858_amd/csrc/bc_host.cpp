@@ -479,10 +479,14 @@ struct HostJob {
     uint32_t root_lo, root_hi;
     bool trivial_zero;
     uint64_t cost;             // planning proxy after the candidate pass
+    uint64_t weight;           // the same over the whole depth (job ordering)
 };
 
+// short_first: order the tasks job by job, cheapest job (by the cost proxy)
+// first, instead of all tasks by cost -- for served batches, where one job
+// that cannot meet its deadline must not hold back the others.
 bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::vector<bc_u128> &out,
-                   std::vector<bc_status> &item_status, bc_stats *stats)
+                   std::vector<bc_status> &item_status, bc_stats *stats, bool short_first = false)
 {
     const size_t ns = specs.size();
     out.assign(ns, bc_u128{0, 0});
@@ -680,7 +684,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         const uint32_t j = cj[c];
         const HostJob &hj = jobs[j];
         const Side &A = specs[hj.spec].g->side[hj.anchor];
-        uint64_t cost = 0;
+        uint64_t cost = 0, weight = 0;
         const uint32_t e = std::min<uint32_t>(hj.pA - 1, 3);
         for (uint64_t r = root_prefix[c]; r < root_prefix[c + 1]; ++r) {
             uint64_t k = h_k[r];
@@ -689,8 +693,12 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             uint64_t x = k * w1;
             for (uint32_t t = 1; t < e; ++t) x = std::min<uint64_t>(x * k, 1ull << 62);
             cost = std::min<uint64_t>(cost + x, 1ull << 62);
+            // the whole depth, for ordering jobs against each other
+            for (uint32_t t = e; t + 1 < hj.pA; ++t) x = std::min<uint64_t>(x * k, 1ull << 62);
+            weight = std::min<uint64_t>(weight + x, 1ull << 62);
         }
         jobs[j].cost = cost;
+        jobs[j].weight = weight;
     }
     for (size_t i = 0; i < ns; ++i) {
         if (spec_jobs[i].size() == 2) {
@@ -725,7 +733,15 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             plan.push_back(Plan{c, u, (uint32_t)k, w1, x, r});
         }
     }
-    std::stable_sort(plan.begin(), plan.end(), [](const Plan &a, const Plan &b) { return a.cost > b.cost; });
+    if (short_first)
+        std::stable_sort(plan.begin(), plan.end(), [&](const Plan &a, const Plan &b) {
+            const uint64_t ca = jobs[cj[a.c]].weight, cb = jobs[cj[b.c]].weight;
+            if (ca != cb) return ca < cb;
+            if (a.c != b.c) return a.c < b.c;
+            return a.cost > b.cost;
+        });
+    else
+        std::stable_sort(plan.begin(), plan.end(), [](const Plan &a, const Plan &b) { return a.cost > b.cost; });
     std::vector<bcdev::ActiveRoot> aroots(plan.size());
     uint64_t pool_words = 0, tasks = 0, slab_need = 64;
     // rows already built by the fused kernel, unless some root found no room
@@ -961,7 +977,7 @@ bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 
     }
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
-    bc_status s = run_jobs(sp, opts, res, ist, nullptr);
+    bc_status s = run_jobs(sp, opts, res, ist, nullptr, true);
     for (size_t t = 0; t < idx.size(); ++t) {
         status[idx[t]] = (s == BC_OK || s == BC_E_DEVICE) && t < ist.size() ? ist[t] : s;
         out[idx[t]] = (status[idx[t]] == BC_OK && t < res.size()) ? res[t] : bc_u128{0, 0};
