@@ -1231,6 +1231,57 @@ __device__ void triple_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m
     wave_sync();
 }
 
+// One row block of the pair sum over m rows (W words, column-major with
+// stride), on the matrix cores: rows a in [16 I, 16 I + 16) against every
+// row b > a, adding C(|row_a & row_b|, q).  The row blocks I = 0, 1, ...
+// together give the whole pair sum; rows past m are zero and add nothing.
+template <int W, bool Lds>
+__device__ void pair_row_block_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t I,
+                                    const uint32_t *t32, Acc &acc)
+{
+    const uint32_t ln = lane_id();
+    const uint32_t r16 = ln & 15;
+    const uint32_t nb = (m + 15) >> 4;
+    const int tb = (int)lds_addr(t32);
+    const v4i c0 = {tb, tb, tb, tb};
+    auto fetch = [&](uint32_t B, uint64_t (&x)[W]) {
+        const uint32_t row = 16 * B + r16;
+        const uint32_t rr = row < m ? row : m - 1;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t v = row_word<Lds>(blk, (uint64_t)w * stride + rr);
+            x[w] = row < m ? v : 0ull;
+        }
+    };
+    uint64_t x[W];
+    fetch(I, x);
+    v4i ea[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) ea[w] = spread_bits<1>(x[w], ln);
+    uint64_t s64 = 0;
+    uint64_t nx[W];
+    fetch(I, nx);
+    for (uint32_t J = I; J < nb; ++J) {
+        v4i eb[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) eb[w] = spread_bits<4>(nx[w], ln);
+        fetch(J + 1, nx);
+        const v4i d = mfma_block<W>(ea, eb, c0);
+        uint32_t s = 0;
+        if (J > I) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += lds_load_u32((uint32_t)d[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                s += lds_load_u32(4 * (ln >> 4) + (uint32_t)i < r16 ? (uint32_t)d[i] : (uint32_t)tb);
+        }
+        s64 += s;
+    }
+    acc.t += s64;
+    acc_flush(acc);
+}
+
 // Children of row a: rows b > a whose AND with row a keeps >= q bits, written
 // (ANDed) into nblk (stride nstride) in order.  Returns their number.
 __device__ uint32_t filter_children(const uint64_t *blk, uint32_t stride, uint32_t m, uint32_t a, uint32_t W,
@@ -1332,6 +1383,30 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     uint64_t t0 = instrument ? cycles() : 0;
 
     const uint32_t rem = k - i - 1;
+    if (pA == 3 && W1 <= kTileWords && du <= jb.n_u28 && table_ready(tb, jb, jidx, du + 1)) {
+        // the root's leaves {u, c_a, c_b} are the pair sum over its rows:
+        // task i = 16 I takes row block I on the matrix cores, the root's
+        // other tasks have nothing left to do
+        if ((i & 15) == 0) {
+            const uint64_t *rows = pool + rt.pool_off;
+            switch (W1) {
+            case 1: pair_row_block_mfma<1, false>(rows, k, k, i >> 4, tb.t32, acc); break;
+            case 2: pair_row_block_mfma<2, false>(rows, k, k, i >> 4, tb.t32, acc); break;
+            case 3: pair_row_block_mfma<3, false>(rows, k, k, i >> 4, tb.t32, acc); break;
+            default: pair_row_block_mfma<4, false>(rows, k, k, i >> 4, tb.t32, acc); break;
+            }
+            if (instrument) {
+                const uint32_t a1 = min(i + 16, k);
+                unsigned long long pr = 0;
+                for (uint32_t a = i; a < a1; ++a) pr += k - 1 - a;
+                ct.pairs += pr;
+                ct.pair_words += pr * W1;
+                ct.pair_slots += 256ull * (((k + 15) >> 4) - (i >> 4));
+            }
+        }
+        if (instrument) ct.cyc_pair += cycles() - t0;
+        return;
+    }
     // S2 = row i (common neighbours of u and c_i).  Its first two nonzero
     // words (s0, s1, at word indices w0, w1) stay in scalar registers; wider
     // roots also get the table of all nonzero words.
