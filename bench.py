@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=200, help="queries per arrival rate")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000")
     ap.add_argument("--serve-graphs", type=int, default=64)
+    ap.add_argument("--serve-batch", type=int, default=8, help="most queries per served batch")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -371,7 +372,7 @@ def run_serve(args):
     solo_cache = {}
     for ri, rate in enumerate(rates):
         t_arr, gid, p, q = gg.poisson_arrivals(rate, args.serve_queries, len(graphs), 2, 8, seed=6000 + int(rate))
-        srv = bc.Server(max_inflight=3, max_batch=64, batch_timeout_ms=deadline_ms)
+        srv = bc.Server(max_inflight=3, max_batch=args.serve_batch, batch_timeout_ms=deadline_ms)
         for G in graphs:
             srv.add_graph(G)
         start = srv.now_ns()
@@ -423,7 +424,8 @@ def run_serve(args):
         "dtype": "u128",
         "data": "synthetic",
         "config": {"workload": "served_chung_lu", "graphs": len(graphs), "edges": sum(g.n_edges for g in raw),
-                   "pq": "U{2..8}^2", "queries_per_rate": args.serve_queries, "deadline_ms": deadline_ms},
+                   "pq": "U{2..8}^2", "queries_per_rate": args.serve_queries, "deadline_ms": deadline_ms,
+                   "max_batch": args.serve_batch},
         "per_rate": per_rate,
     }
     print(json.dumps(line), flush=True)

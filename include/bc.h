@@ -66,7 +66,8 @@ typedef struct {
     void *stream;              /* hipStream_t to run on; NULL = the library's own stream */
     int32_t anchor;            /* BC_ANCHOR_AUTO / _U / _V */
     uint32_t lds_words;        /* per-wavefront LDS budget in 64-bit words; 0 = default */
-    uint32_t waves_per_cu;     /* persistent-grid occupancy target; 0 = default */
+    uint32_t waves_per_cu;     /* persistent-grid occupancy target, 1..12 wavefronts per CU (larger is
+                                  capped); 0 = default (12) */
     uint32_t instrument;       /* nonzero: fill the work counters of bc_stats */
     uint32_t timeout_ms;       /* device-side time limit of the call (0 = none); past it the
                                   call fails with BC_E_TIMEOUT and no count is returned */

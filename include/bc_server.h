@@ -11,6 +11,14 @@
  * batches already running (continuous batching).  The paper has no serving
  * layer; the counting work inside each batch is the one of Algorithm 1.
  *
+ * Sharing: each of the max_inflight workers runs its enumeration on its
+ * share of the device's wave slots (bc_opts.waves_per_cu), so batches in
+ * flight progress together instead of waiting for the GPU in turn.
+ *
+ * Order: a free batch slot takes the newest pending queries first.  Under
+ * overload the oldest would start with little of their deadline left and
+ * expire one after another; newest-first keeps answering some queries.
+ *
  * Memory admission: each query is charged an estimate of its device scratch
  * (candidate-pass scratch + bitmap rows + enumeration slabs, from the graph's
  * sizes); a batch only starts while the estimates in flight stay within

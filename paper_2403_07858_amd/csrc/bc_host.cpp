@@ -317,48 +317,65 @@ struct JobSpec {
     uint64_t deadline_ns;      // steady clock, 0 = none
 };
 
-// Device real-time clock against the host steady clock, per device: two
-// samples 20 ms apart give the tick rate, the second one the offset.
+// Device real-time clock against the host steady clock, per device.  The
+// counter runs at a constant 100 MHz; two samples 20 ms apart check that
+// rate once (a rate off by more than 2 % is used as measured instead).  Each
+// call re-anchors the offset with a fresh sample taken on the caller's
+// (idle) stream, kept only when its round trip was short, so that an error in
+// the rate cannot accumulate over the life of the process.
 struct ClockCal {
     bool ok = false;
     double ticks_per_ns = 0.1;
     double offset = 0.0;
 };
 
+// One sample: the device tick and the host time at the middle of the round
+// trip; false on a HIP error.
+bool clock_sample(uint64_t *d, hipStream_t st, uint64_t &tick, double &mid, uint64_t &rtt)
+{
+    const uint64_t t0 = bcint::steady_ns();
+    hipError_t e = bcdev::launch_read_clock(d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&tick, d, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const uint64_t t1 = bcint::steady_ns();
+    mid = 0.5 * ((double)t0 + (double)t1);
+    rtt = t1 - t0;
+    return e == hipSuccess;
+}
+
 bc_status device_clock(int device, hipStream_t st, ClockCal &out)
 {
     static std::mutex mu;
     static std::vector<ClockCal> cache(64);
-    std::lock_guard<std::mutex> g(mu);
     if (device < 0 || device >= 64) return set_error(BC_E_DEVICE, "device id out of range");
-    if (cache[device].ok) {
-        out = cache[device];
-        return BC_OK;
-    }
+    // stream-ordered scratch: a plain free would wait for the whole device
     uint64_t *d = nullptr;
-    BC_HIP(hipMalloc(&d, 8));
-    double mid[2];
-    uint64_t tick[2];
-    for (int i = 0; i < 2; ++i) {
-        if (i) std::this_thread::sleep_for(std::chrono::milliseconds(20));
-        uint64_t t0 = bcint::steady_ns();
-        hipError_t e = bcdev::launch_read_clock(d, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(&tick[i], d, 8, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        uint64_t t1 = bcint::steady_ns();
-        if (e != hipSuccess) {
-            (void)hipFree(d);
-            return hip_error(e, "clock calibration");
-        }
-        mid[i] = 0.5 * ((double)t0 + (double)t1);
+    BC_HIP(hipMallocAsync((void **)&d, 8, st));
+    uint64_t tick = 0, rtt = 0;
+    double mid = 0;
+    if (!clock_sample(d, st, tick, mid, rtt)) {
+        (void)hipFreeAsync(d, st);
+        return set_error(BC_E_DEVICE, "clock calibration failed");
     }
-    (void)hipFree(d);
-    ClockCal c;
-    c.ok = true;
-    c.ticks_per_ns = (double)(tick[1] - tick[0]) / (mid[1] - mid[0]);
-    if (!(c.ticks_per_ns > 0)) c.ticks_per_ns = 0.1;   // nominal 100 MHz
-    c.offset = (double)tick[1] - c.ticks_per_ns * mid[1];
-    cache[device] = c;
+    std::lock_guard<std::mutex> g(mu);
+    ClockCal &c = cache[device];
+    if (!c.ok) {
+        // rate check: a second sample 20 ms later
+        std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        uint64_t tick2 = 0, rtt2 = 0;
+        double mid2 = 0;
+        if (!clock_sample(d, st, tick2, mid2, rtt2)) {
+            (void)hipFreeAsync(d, st);
+            return set_error(BC_E_DEVICE, "clock calibration failed");
+        }
+        const double rate = (double)(tick2 - tick) / (mid2 - mid);
+        c.ticks_per_ns = (rate > 0.098 && rate < 0.102) || !(rate > 0) ? 0.1 : rate;
+        c.offset = (double)tick2 - c.ticks_per_ns * mid2;
+        c.ok = true;
+    } else if (rtt < 2000000) {
+        c.offset = (double)tick - c.ticks_per_ns * mid;
+    }
+    (void)hipFreeAsync(d, st);
     out = c;
     return BC_OK;
 }
@@ -421,11 +438,12 @@ int cu_count(int device)
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0) v = 256;
         cache[device] = v;
-        // keep stream-ordered allocations cached between calls instead of
-        // returning them to the driver at every synchronization
+        // keep up to 32 GiB of stream-ordered allocations cached between
+        // calls instead of returning them to the driver at every
+        // synchronization (more would starve other users of the device)
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-            uint64_t thr = ~0ull;
+            uint64_t thr = 32ull << 30;
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
         }
     }
@@ -497,7 +515,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     const int device = specs[0].g->device;
     BC_HIP(hipSetDevice(device));
     const uint32_t lds_words = (opts && opts->lds_words) ? opts->lds_words : bcdev::max_lds_words_per_wave();
-    const uint32_t waves_per_cu = (opts && opts->waves_per_cu) ? std::max(4u, opts->waves_per_cu) : 12u;
+    const uint32_t waves_per_cu = (opts && opts->waves_per_cu) ? std::min(12u, opts->waves_per_cu) : 12u;
     const bool instrument = opts && opts->instrument;
     const int ncu = cu_count(device);
     auto t_host0 = std::chrono::steady_clock::now();
@@ -618,9 +636,13 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     std::vector<uint32_t> cj;   // jobs in the candidate pass
     std::vector<uint64_t> root_prefix(1, 0);
     uint32_t nA_max = 1;
-    for (uint32_t j = 0; j < nj; ++j) {
-        if (jobs[j].trivial_zero || jobs[j].pA < 2) continue;
-        cj.push_back(j);
+    for (uint32_t j = 0; j < nj; ++j)
+        if (!jobs[j].trivial_zero && jobs[j].pA >= 2) cj.push_back(j);
+    if (short_first)   // served batches: the small graphs' candidate passes first
+        std::stable_sort(cj.begin(), cj.end(), [&](uint32_t a, uint32_t b) {
+            return specs[jobs[a].spec].g->nnz < specs[jobs[b].spec].g->nnz;
+        });
+    for (uint32_t j : cj) {
         root_prefix.push_back(root_prefix.back() + (jobs[j].root_hi - jobs[j].root_lo));
         nA_max = std::max(nA_max, hjobs[j].nA);
     }
@@ -662,8 +684,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             uint64_t *d_off;
             BC_HIP(mem.get(&d_off, total_roots));
             BC_HIP(mem.get(&d_pool_fused, pool_cap));
-            // one block of kRbThreads per CU (its LDS table takes most of the CU's LDS)
-            const uint32_t fused_blocks = (uint32_t)std::min<uint64_t>(total_roots, (uint64_t)ncu);
+            // one block of kRbThreads per CU (its LDS table takes most of the
+            // CU's LDS); a reduced waves_per_cu takes the same share of CUs
+            const uint32_t fused_blocks = (uint32_t)std::min<uint64_t>(
+                total_roots, std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
             BC_HIP(bcdev::launch_root_build(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, d_pool_fused, pool_cap,
                                             fused_blocks, d_queue + 4, d_k, d_off, d_slots, st));
             h_off.resize(total_roots);
@@ -988,12 +1012,12 @@ bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 
 uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q)
 {
     // candidate-pass scratch (3 u32 arrays per block over the anchor side),
-    // the per-root rows (bounded by 16 B per edge in practice) and a share of
-    // the enumeration slabs.
+    // the row pool of the fused per-root kernel (32 words per edge plus
+    // 32 MiB) and a share of the enumeration slabs.
     (void)q;
     const uint64_t n = std::max(g->side[0].n, g->side[1].n);
     const uint64_t blocks = 2ull * 256;
-    return blocks * n * 12 + 16 * g->nnz + (uint64_t)std::max<uint32_t>(p, 1) * (64ull << 20);
+    return blocks * n * 12 + 256 * g->nnz + (32ull << 20) + (uint64_t)std::max<uint32_t>(p, 1) * (64ull << 20);
 }
 
 int graph_device(const bc_graph *g) { return g->device; }

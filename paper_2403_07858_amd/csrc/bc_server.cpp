@@ -78,7 +78,11 @@ void finish(bc_server *s, Ticket &t, bc_status st, bc_u128 v, uint64_t now)
 void worker_main(bc_server *s)
 {
     hipStream_t stream = nullptr;
-    if (!s->graphs.empty()) (void)hipSetDevice(bcint::graph_device(s->graphs[0]));
+    {
+        // graphs may still be being added (the vector can reallocate)
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->graphs.empty()) (void)hipSetDevice(bcint::graph_device(s->graphs[0]));
+    }
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
     const uint32_t max_batch = s->opts.max_batch ? s->opts.max_batch : 256;
     for (;;) {
@@ -100,13 +104,17 @@ void worker_main(bc_server *s)
                         ++it;
                     }
                 }
-                // admit in arrival order while the memory budget allows
+                // admit newest first while the memory budget allows: when
+                // queries arrive faster than they can be answered, taking the
+                // oldest would start only queries with little time left, so
+                // every query would expire; the newest have their whole
+                // deadline ahead of them
                 while (!s->pending.empty() && batch.size() < max_batch) {
-                    Ticket &t = s->tickets[s->pending.front()];
+                    Ticket &t = s->tickets[s->pending.back()];
                     if (s->inflight_bytes + batch_bytes + t.est_bytes > s->opts.memory_budget_bytes) break;
                     batch_bytes += t.est_bytes;
-                    batch.push_back(s->pending.front());
-                    s->pending.pop_front();
+                    batch.push_back(s->pending.back());
+                    s->pending.pop_back();
                 }
                 if (!batch.empty()) break;
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
@@ -147,6 +155,10 @@ void worker_main(bc_server *s)
         o.struct_size = sizeof(bc_opts);
         o.stream = stream;
         o.anchor = BC_ANCHOR_AUTO;
+        // the enumeration grid is persistent: at full size one batch would
+        // hold every CU until it ends, and the batches of the other workers
+        // could not start; each worker takes its share of the wave slots
+        o.waves_per_cu = std::max(1u, 12u / std::max(1u, s->opts.max_inflight));
         bc_status rc = bcint::count_queries(qs.data(), qs.size(), &o, out.data(), st.data());
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -179,6 +191,12 @@ extern "C" bc_status bc_server_create(const bc_server_opts *opts, bc_server **ou
     if (!s->opts.max_batch) s->opts.max_batch = 256;
     if (!s->opts.max_pending) s->opts.max_pending = 65536;
     if (!s->opts.memory_budget_bytes) {
+        // memory cached by earlier counts is not in use: give it back first
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
+            hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+            (void)hipMemPoolTrimTo(pool, 0);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) free_b = 8ull << 30;
         s->opts.memory_budget_bytes = free_b / 2;
