@@ -285,6 +285,12 @@ def run_batch(args):
     _log(f"[batch] built {len(graphs)} graphs in {time.time() - t0:.1f}s")
     opt = {"stream": stream, "timeout_ms": args.timeout_ms}
 
+    # the batched path's autotuner picks the schedule on a sample of the items
+    t0 = time.perf_counter()
+    tuned = bc.bc_tune_batch(graphs, ps, qs, stream=stream, timeout_ms=args.timeout_ms)
+    t_tune = time.perf_counter() - t0
+    _log(f"[batch] autotuner chose {tuned} in {t_tune * 1e3:.0f} ms")
+    opt.update(tuned)
     # warmup: the batched path once, instrumented
     vals, st, agg = bc.bc_count_batch(graphs, ps, qs, with_stats=True, instrument=True, **opt)
     cyc = {k: agg[k] for k in ("cyc_setup", "cyc_compact", "cyc_pair", "cyc_filter")}
@@ -346,6 +352,8 @@ def run_batch(args):
                    "timeout_ms": args.timeout_ms},
         "bicliques_per_s": total / t_batch,
         "batched_vs_per_query_speedup": t_single / t_batch,
+        "schedule": tuned,
+        "autotune_ms": t_tune * 1e3,
         "per_query_ms_total": t_single * 1e3,
         "completed": ok,
         "statuses": {bc.bc_status_string(s): st.count(s) for s in set(st)},

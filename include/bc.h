@@ -153,6 +153,19 @@ bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, int32_t anch
 bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q,
                          size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st);
 
+/*
+ * bc_tune_batch -- chooses a schedule for bc_count_batch over the same items
+ * (the paper has no batching; this is the batched path's autotuner).  The
+ * candidates are the persistent-grid occupancy (bc_opts.waves_per_cu 12, 8,
+ * 4) and the per-wavefront LDS arena (bc_opts.lds_words 600, 256); each is
+ * timed on an evenly spaced sample of the items (every 16th, at least 8) and
+ * *tuned receives base (NULL = defaults) with the fastest pair.  No count
+ * depends on these options.  A sample item that fails (e.g. over base's time
+ * limit) counts as taking the whole limit.  Returns argument or device errors.
+ */
+bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
+                        const bc_opts *base, bc_opts *tuned);
+
 /* Human-readable name of a status code (static storage). */
 const char *bc_status_string(bc_status s);
 

@@ -83,6 +83,7 @@ def _load():
         "bc_count": ([P, U32, U32, P, P, P], I32),
         "bc_count_roots": ([P, U32, U32, I32, U64, U64, P, P, P], I32),
         "bc_count_batch": ([P, P, P, SZ, P, P, P, P], I32),
+        "bc_tune_batch": ([P, P, P, SZ, P, P], I32),
         "bc_status_string": ([I32], ctypes.c_char_p),
         "bc_last_error": ([], ctypes.c_char_p),
     }
@@ -96,7 +97,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_count", "bc_count_roots", "bc_count_batch",
-            "bc_status_string", "bc_last_error")
+            "bc_tune_batch", "bc_status_string", "bc_last_error")
 
 
 class BCError(RuntimeError):
@@ -245,6 +246,21 @@ def bc_count_batch(graphs, ps, qs, with_stats=False, **opt):
         raise BCError(s, "bc_count_batch")
     res = ([out[i].value for i in range(n)], [int(x) for x in st[:n]])
     return res + (agg.as_dict(),) if with_stats else res
+
+
+def bc_tune_batch(graphs, ps, qs, **opt) -> dict:
+    """Schedule options chosen for bc_count_batch over these items:
+    {"waves_per_cu": ..., "lds_words": ...} (pass them on with **)."""
+    n = len(graphs)
+    hs = (ctypes.c_void_p * max(1, n))(*[g.handle for g in graphs])
+    pa = np.ascontiguousarray(ps, dtype=np.uint32)
+    qa = np.ascontiguousarray(qs, dtype=np.uint32)
+    base = make_opts(**opt)
+    tuned = bc_opts()
+    s = _lib.bc_tune_batch(hs, pa.ctypes.data, qa.ctypes.data, n, ctypes.byref(base), ctypes.byref(tuned))
+    if s != BC_OK:
+        raise BCError(s, "bc_tune_batch")
+    return {"waves_per_cu": tuned.waves_per_cu, "lds_words": tuned.lds_words}
 
 
 # ---------------------------------------------------------------------------

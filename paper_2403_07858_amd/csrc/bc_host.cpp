@@ -977,6 +977,51 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
     return s;
 }
 
+extern "C" bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
+                                   const bc_opts *base, bc_opts *tuned)
+{
+    g_last_error.clear();
+    if (!tuned || (n && (!graphs || !p || !q))) return set_error(BC_E_INVALID_ARG, "bc_tune_batch: NULL argument");
+    if (bc_status s = check_opts(base)) return s;
+    bc_opts b{};
+    if (base) b = *base;
+    b.struct_size = sizeof(bc_opts);
+    *tuned = b;
+    if (n == 0) return BC_OK;
+    // evenly spaced sample: every step-th item, at least 8 items when there are
+    const size_t want = std::max<size_t>(8, n / 16);
+    const size_t step = std::max<size_t>(1, n / want);
+    std::vector<const bc_graph *> sg;
+    std::vector<uint32_t> sp, sq;
+    for (size_t i = 0; i < n; i += step) {
+        sg.push_back(graphs[i]);
+        sp.push_back(p[i]);
+        sq.push_back(q[i]);
+    }
+    std::vector<bc_u128> out(sg.size());
+    std::vector<bc_status> st(sg.size());
+    const uint32_t waves[3] = {12, 8, 4};
+    const uint32_t lds[2] = {0, 256};   // 0 = the default arena
+    double best = -1.0;
+    for (uint32_t w : waves)
+        for (uint32_t l : lds) {
+            bc_opts c = b;
+            c.waves_per_cu = w;
+            c.lds_words = l;
+            const uint64_t t0 = bcint::steady_ns();
+            bc_status s = bc_count_batch(sg.data(), sp.data(), sq.data(), sg.size(), &c, out.data(), st.data(), nullptr);
+            if (s != BC_OK) return s;
+            double t = (double)(bcint::steady_ns() - t0);
+            for (bc_status x : st)
+                if (x != BC_OK && b.timeout_ms) t += (double)b.timeout_ms * 1e6;
+            if (best < 0 || t < best) {
+                best = t;
+                *tuned = c;
+            }
+        }
+    return BC_OK;
+}
+
 namespace bcint {
 
 uint64_t steady_ns()

@@ -183,6 +183,12 @@ def test_batch_matches_single(bc):
         say("batch", i, ps[i], qs[i], want)
         assert vals[i] == want
         assert bc.bc_count(graphs[i], ps[i], qs[i]) == want
+    # the autotuner's schedule gives the same counts
+    tuned = bc.bc_tune_batch(graphs, ps, qs)
+    say("tuned", tuned)
+    assert tuned["waves_per_cu"] in (12, 8, 4) and tuned["lds_words"] in (0, 256)
+    vals2, st2 = bc.bc_count_batch(graphs, ps, qs, **tuned)
+    assert st2 == st and vals2 == vals
 
 
 # ---------------------------------------------------------------------------
