@@ -92,3 +92,17 @@ def test_null_and_range_arguments(bc):
     assert lib.bc_graph_info(None, None, None, None) == bc.BC_E_INVALID_ARG
     lib.bc_free(None)  # NULL is ignored
     assert out.lo == 0 and out.hi == 0
+
+
+def test_tune_batch_argument_errors(bc):
+    lib = ctypes.CDLL(bc.LIB_PATH)
+    lib.bc_tune_batch.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_size_t] + [ctypes.c_void_p] * 2
+    lib.bc_tune_batch.restype = ctypes.c_int32
+    # no output, or items without arrays: refused before any device work
+    assert lib.bc_tune_batch(None, None, None, 0, None, None) == bc.BC_E_INVALID_ARG
+    tuned = bc.bc_opts()
+    assert lib.bc_tune_batch(None, None, None, 3, None, ctypes.byref(tuned)) == bc.BC_E_INVALID_ARG
+    # an empty batch keeps the base options
+    base = bc.make_opts(waves_per_cu=8, lds_words=256)
+    assert lib.bc_tune_batch(None, None, None, 0, ctypes.byref(base), ctypes.byref(tuned)) == bc.BC_OK
+    assert tuned.waves_per_cu == 8 and tuned.lds_words == 256
