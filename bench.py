@@ -30,6 +30,7 @@ OPS_PER_WORD_PAIR = 2 * 64
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
 # 1 GiB device copy), valid only for the kernel source they were taken on.
 TRAFFIC_KERNEL_SHA256_PREFIX = "174d3ac36c929cf3"
+TRAFFIC_WORKLOAD = "power_law_2m"
 TRAFFIC_BYTES_Q44 = (1190382 * 2.0 + 5578662 * 1.0) * 1024
 
 WORKLOADS = {
@@ -194,21 +195,25 @@ def main():
         "root_vertices_per_s": roots / (ms_per_step / 1000),
         "per_query": per_query,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_I8_PEAK / 1e12,
-                     "unit": "TOP/s", "dtype": "int8", "frac": achieved / MFMA_I8_PEAK, "traffic": traffic_bytes(queries),
-                     "traffic_unit": "bytes per k_enumerate launch of (4,4)", "kernel": "k_enumerate"},
+                     "unit": "TOP/s", "dtype": "int8", "frac": achieved / MFMA_I8_PEAK,
+                     "traffic": traffic_bytes(args.workload, queries),
+                     "traffic_unit": f"bytes per k_enumerate launch of (4,4) on {TRAFFIC_WORKLOAD}",
+                     "kernel": "k_enumerate"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
 
-def traffic_bytes(queries):
-    """Measured HBM bytes of the (4,4) enumeration launch, or None when the
-    kernel source changed since the counters were taken or (4,4) is not run."""
+def traffic_bytes(workload, queries):
+    """Measured HBM bytes of the (4,4) enumeration launch on the 2M-edge graph,
+    or None when the kernel source changed since the counters were taken, or
+    the workload is another graph, or (4,4) is not run."""
     import hashlib
     src = os.path.join(ROOT, "paper_2403_07858_amd", "csrc", "bc_kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if not sha.startswith(TRAFFIC_KERNEL_SHA256_PREFIX) or (4, 4) not in queries:
+    if (not sha.startswith(TRAFFIC_KERNEL_SHA256_PREFIX) or workload != TRAFFIC_WORKLOAD
+            or (4, 4) not in queries):
         return None
     return TRAFFIC_BYTES_Q44
 

@@ -305,6 +305,57 @@ __device__ __forceinline__ void wedges_flat(const Job &jb, uint64_t ub, uint32_t
     }
 }
 
+// wedges_flat that stops early once *over is raised (by f or another wave).
+// With Count, f returns true when its wedge claimed a new table slot; each
+// wave adds its claims per step, and once the block total passes cap the
+// waves raise *over (the caller then discards the table).
+template <int NW, bool Count, typename F>
+__device__ __forceinline__ void wedges_flat_capped(const Job &jb, uint64_t ub, uint32_t du, uint32_t cap,
+                                                   uint32_t *claimed, volatile uint32_t *over, F f)
+{
+    const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
+    for (uint32_t j0 = 0; j0 < du; j0 += kWaveSize) {
+        const uint32_t j = j0 + ln;
+        uint64_t s = 0;
+        uint32_t len = 0;
+        if (j < du) {
+            const uint32_t v = jb.adjA[ub + j];
+            s = jb.ptrB[v] + jb.rposA[ub + j] + 1;
+            len = (uint32_t)(jb.ptrB[v + 1] - s);
+        }
+        const uint32_t inc = wave_inclusive_scan(len);
+        const uint32_t excl = inc - len;
+        const uint64_t base = s - excl;
+        const uint32_t total = __shfl(inc, kWaveSize - 1);
+        for (uint32_t x0 = wv * kWaveSize; x0 < total; x0 += 2 * NW * kWaveSize) {
+            const uint32_t xa = x0 + ln, xb = xa + NW * kWaveSize;
+            uint32_t la = 0, lb = 0;
+#pragma unroll
+            for (uint32_t b = 32; b; b >>= 1) {
+                if (__shfl(excl, (int)(la + b)) <= xa) la += b;
+                if (__shfl(excl, (int)(lb + b)) <= xb) lb += b;
+            }
+            const uint64_t pa = bcast64(base, (int)la) + xa, pb = bcast64(base, (int)lb) + xb;
+            uint32_t wa = 0, wb = 0;
+            if (xa < total) wa = jb.adjB[pa];
+            if (xb < total) wb = jb.adjB[pb];
+            bool na = false, nb = false;
+            if (xa < total) na = f(du - 1 - (j0 + la), wa);
+            if (xb < total) nb = f(du - 1 - (j0 + lb), wb);
+            if constexpr (Count) {
+                const uint32_t nn = (uint32_t)__popcll(__ballot(na)) + (uint32_t)__popcll(__ballot(nb));
+                uint32_t tot = 0;
+                if (nn) {
+                    if (ln == 0) tot = atomicAdd(claimed, nn) + nn;
+                    tot = __shfl(tot, 0);
+                    if (tot > cap && ln == 0) *over = 1u;
+                }
+            }
+            if (*over) return;
+        }
+    }
+}
+
 // k_cand_count: for every root of every job, k(u) = #{w > u : |N(u) n N(w)| >= qA}.
 // Common-neighbour counts live in a per-block dense counter array (all zero
 // between roots); the ids touched are listed so that only they are reset.
@@ -531,6 +582,9 @@ constexpr uint32_t kHashSlots = 8192;       // LDS table entries
 constexpr uint32_t kHashProbes = 128;       // longest probe sequence before falling back
 constexpr uint32_t kSlotsPerThread = kHashSlots / kRbThreads;
 constexpr uint16_t kNoRow = 0xffffu;
+constexpr uint32_t kHintDistinct = 8192;    // 2-hop vertices above which the next root starts with id ranges
+constexpr uint32_t kCapRange = 5120;        // distinct 2-hop vertices of one id range
+constexpr uint32_t kRowsCap = 4096;         // candidates of a root counted by id ranges
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - 13); }
 
@@ -548,6 +602,40 @@ __device__ __forceinline__ int hash_insert(uint32_t *key, uint32_t w)
         }
     }
     return -1;
+}
+
+// As hash_insert; *fresh tells whether this call claimed the slot.
+__device__ __forceinline__ int hash_insert_new(uint32_t *key, uint32_t w, bool *fresh)
+{
+    const uint32_t kv = w + 1u;
+    uint32_t h = hash_slot(w);
+    *fresh = false;
+    for (uint32_t p = 0; p < kHashProbes; ++p, h = (h + 1) & (kHashSlots - 1)) {
+        const uint32_t e = key[h];
+        if (e == kv) return (int)h;
+        if (e == 0u) {
+            const uint32_t old = atomicCAS(&key[h], 0u, kv);
+            if (old == 0u) {
+                *fresh = true;
+                return (int)h;
+            }
+            if (old == kv) return (int)h;
+        }
+    }
+    return -1;
+}
+
+// Slot of w, or -1 when w is absent (the table must have an empty slot).
+__device__ __forceinline__ int hash_lookup(const uint32_t *key, uint32_t w)
+{
+    const uint32_t kv = w + 1u;
+    uint32_t h = hash_slot(w);
+    for (;;) {
+        const uint32_t e = key[h];
+        if (e == kv) return (int)h;
+        if (e == 0u) return -1;
+        h = (h + 1) & (kHashSlots - 1);
+    }
 }
 
 // Slot of w (w must be present).
@@ -590,7 +678,7 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
     __shared__ uint32_t s_sort[kHashSlots];              // candidates being sorted
     __shared__ uint32_t s_wsum[kRbWaves];
     __shared__ unsigned long long s_item, s_off;
-    __shared__ uint32_t s_k, s_nt, s_flag;
+    __shared__ uint32_t s_k, s_nt, s_flag, s_claimed;
     unsigned long long *queue = counters;        // roots
     unsigned long long *pool_head = counters + 1;
     uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
@@ -605,6 +693,7 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
     u128 acc = 0;
     bool ovf = false;
     uint32_t cur_job = 0xffffffffu;
+    uint32_t parts_hint = 1;   // id ranges the previous root needed
     for (;;) {
         if (tid == 0) {
             s_item = atomicAdd(queue, 1ull);
@@ -612,6 +701,7 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
             s_nt = 0;
             s_flag = 0;
             s_off = ~0ull;
+            s_claimed = 0;
         }
         __syncthreads();
         const uint64_t item = s_item;
@@ -646,18 +736,150 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
         const bool rows = jb.pA >= 3;
 
         // pass 1: insert every 2-hop vertex; one-word roots OR in the row bit,
-        // wider ones count
-        wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t jj, uint32_t w) {
-            const int h = hash_insert(s_key, w);
-            if (h < 0) s_flag = 1;
-            else if (one) atomicOr(&s_row[h], 1ull << jj);
-            else atomicAdd(&s_row[h], 1ull);
-        });
-        __syncthreads();
-        const bool in_lds = s_flag == 0;
+        // wider ones count.  It gives up at the first insert that finds no
+        // slot within kHashProbes, and is skipped when the previous root of
+        // this block needed several id ranges.
+        volatile uint32_t *flag = &s_flag;
+        bool in_lds = false;
+        if (parts_hint == 1) {
+            wedges_flat_capped<kRbWaves, false>(jb, ub, du, 0, &s_claimed, flag, [&](uint32_t jj, uint32_t w) {
+                const int h = hash_insert(s_key, w);
+                if (h < 0) *flag = 1u;
+                else if (one) atomicOr(&s_row[h], 1ull << jj);
+                else atomicAdd(&s_row[h], 1ull);
+                return false;
+            });
+            __syncthreads();
+            in_lds = s_flag == 0;
+            if (in_lds) parts_hint = 1;
+        }
         uint32_t k = 0;
         uint64_t off = ~0ull;
         bool build = false;
+        bool done = in_lds;
+        if (!in_lds) {
+            // The candidates are the ids above u.  Take them in id ranges, each
+            // counted in a fresh table of at most kCapRange distinct vertices;
+            // a range that passes it is halved and counted again, and the width
+            // doubles after a sparse range.  Candidates are listed in s_sort.
+            const uint32_t lo0 = u + 1u, span = jb.nA - lo0;
+            const uint32_t parts = parts_hint > 2u ? parts_hint : 2u;
+            uint32_t width = (uint32_t)(((uint64_t)span + parts - 1) / parts);
+            uint32_t lo = lo0, distinct = 0;
+            bool fits = true;
+            while (lo < jb.nA) {
+                const uint32_t hi = lo + (width < jb.nA - lo ? width : jb.nA - lo);
+                for (uint32_t x = tid; x < kHashSlots; x += kRbThreads) {
+                    s_key[x] = 0;
+                    s_row[x] = 0;
+                }
+                if (tid == 0) {
+                    s_flag = 0;
+                    s_claimed = 0;
+                }
+                __syncthreads();
+                wedges_flat_capped<kRbWaves, true>(jb, ub, du, kCapRange, &s_claimed, flag, [&](uint32_t jj, uint32_t w) {
+                    if (w < lo || w >= hi) return false;
+                    bool fresh;
+                    const int h = hash_insert_new(s_key, w, &fresh);
+                    if (h < 0) {
+                        *flag = 1u;
+                        return false;
+                    }
+                    if (one) atomicOr(&s_row[h], 1ull << jj);
+                    else atomicAdd(&s_row[h], 1ull);
+                    return fresh;
+                });
+                __syncthreads();
+                const uint32_t over = s_flag, d = s_claimed;
+                __syncthreads();   // read by all before thread 0 resets them
+                if (over) {
+                    width = (hi - lo) >> 1;   // a range of one id cannot overflow
+                    if (width == 0) width = 1;
+                    continue;
+                }
+                distinct += d;
+                uint32_t mine = 0;
+#pragma unroll
+                for (uint32_t i = 0; i < kSlotsPerThread; ++i) {
+                    const uint32_t h = h0 + i;
+                    const unsigned long long e = s_row[h];
+                    const uint32_t c = one ? (uint32_t)__popcll(e) : (uint32_t)e;
+                    if (s_key[h] != 0u && c >= jb.qA) {
+                        ++mine;
+                        if (rows) continue;
+                        if (c >= jb.n_ovf) ovf = true;
+                        else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                    }
+                }
+                uint32_t kk;
+                uint32_t pos = block_excl_scan(mine, s_wsum, &kk);
+                if (rows) {
+                    if (k + kk > kRowsCap) {
+                        fits = false;
+                        break;
+                    }
+#pragma unroll
+                    for (uint32_t i = 0; i < kSlotsPerThread; ++i) {
+                        const uint32_t h = h0 + i;
+                        const unsigned long long e = s_row[h];
+                        const uint32_t c = one ? (uint32_t)__popcll(e) : (uint32_t)e;
+                        const uint32_t kv = s_key[h];
+                        if (kv != 0u && c >= jb.qA) s_sort[k + pos++] = kv - 1u;
+                    }
+                }
+                k += kk;
+                lo = hi;
+                if (4u * d < kCapRange) width = (uint32_t)(2ull * width < span ? 2ull * width : span);
+                __syncthreads();   // table and s_wsum reads done before the next range
+            }
+            parts_hint = distinct > kHintDistinct ? (distinct + kCapRange - 1) / kCapRange : 1u;
+            done = fits;
+            if (fits) {
+                build = rows && k >= jb.pA - 1;
+                if (build && tid == 0) {
+                    const unsigned long long need = (unsigned long long)k * W1;
+                    const unsigned long long o = atomicAdd(pool_head, need);
+                    if (o + need <= pool_cap) s_off = o;
+                }
+                __syncthreads();
+                off = s_off;
+                if (build && off != ~0ull) {
+                    // rows in increasing id order; a table of the candidates alone
+                    // (at most half full) maps an id to its row
+                    block_sort_u32<kRbThreads>(s_sort, k);
+                    for (uint32_t x = tid; x < kHashSlots; x += kRbThreads) s_key[x] = 0;
+                    __syncthreads();
+                    for (uint32_t x = tid; x < k; x += kRbThreads) {
+                        const uint32_t kv = s_sort[x] + 1u;
+                        uint32_t h = hash_slot(kv - 1u);
+                        while (atomicCAS(&s_key[h], 0u, kv) != 0u) h = (h + 1) & (kHashSlots - 1);
+                        s_map[h] = (uint16_t)x;
+                    }
+                    const uint64_t words = (uint64_t)k * W1;
+                    const bool lds_rows = words <= kHashSlots;
+                    if (lds_rows)
+                        for (uint32_t x = tid; x < words; x += kRbThreads) s_row[x] = 0;
+                    else
+                        for (uint64_t x = tid; x < words; x += kRbThreads) pool[off + x] = 0;
+                    __threadfence();
+                    __syncthreads();
+                    wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t jj, uint32_t w) {
+                        const int h = hash_lookup(s_key, w);
+                        if (h >= 0) {
+                            const uint64_t x = (uint64_t)(jj >> 6) * k + s_map[h];
+                            if (lds_rows) atomicOr(&s_row[x], 1ull << (jj & 63));
+                            else atomicOr((unsigned long long *)&pool[off + x], 1ull << (jj & 63));
+                        }
+                    });
+                    __syncthreads();
+                    if (lds_rows)
+                        for (uint32_t x = tid; x < words; x += kRbThreads) pool[off + x] = s_row[x];
+                }
+            } else {
+                k = 0;
+            }
+        }
         if (in_lds) {
             // candidates: count >= qA, indexed in slot order (pA == 2 sums its leaves here)
             uint32_t mine = 0;
@@ -725,8 +947,9 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
                         for (uint32_t x = tid; x < words; x += kRbThreads) pool[off + x] = s_row[x];
                 }
             }
-        } else {
-            // too many distinct 2-hop vertices: count again in the dense array
+        }
+        if (!done) {
+            // too many candidates for the id ranges: count again in the dense array
             wedges_flat<kRbWaves>(jb, ub, du, [&](uint32_t, uint32_t w) {
                 if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
             });

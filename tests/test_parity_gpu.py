@@ -251,3 +251,47 @@ def test_big_side_swap(bc, big):
     # (4,6) with L on U equals (6,4) of the transposed graph, i.e. (4,6) with L on V
     assert a == c
     assert bc.bc_count(G, 6, 4) == b
+
+
+# ---------------------------------------------------------------------------
+# Hub-heavy Chung-Lu graph (20000 x 1500, 200k edges, V degrees up to ~5000):
+# about a quarter of the U roots have more distinct oriented 2-hop vertices
+# than one LDS table holds at a low load, so their candidates are counted by
+# id ranges; at q = 2 a few have more candidates than that path lists and
+# are counted in HBM instead; at q = 1 every 2-hop vertex is a candidate.
+
+@pytest.fixture(scope="module")
+def hubs(bc):
+    g = gg.chung_lu_bipartite(20000, 1500, 200000, 2.5, 1.5, 200, 6000, 5)
+    return g, bc.build_graph(g)
+
+
+def test_hubs_whole_graph(bc, hubs):
+    g, G = hubs
+    dv = g.degrees_v()
+    got = bc.bc_count(G, 3, 1, anchor=bc.BC_ANCHOR_U)
+    say("hubs (3,1) on U", got)
+    assert got == sum(math.comb(int(d), 3) for d in dv)
+    for p, q, anchor in ((2, 2, bc.BC_ANCHOR_U), (2, 3, bc.BC_ANCHOR_U), (3, 2, bc.BC_ANCHOR_U),
+                         (3, 2, bc.BC_ANCHOR_V)):
+        want = oracle.count(g, p, q, anchor="U" if p <= 2 else "V")
+        got = bc.bc_count(G, p, q, anchor=anchor)
+        say("hubs", (p, q), anchor, got, want)
+        assert got == want
+
+
+def test_hubs_per_root(bc, hubs):
+    g, G = hubs
+    ranks = list(range(0, g.n_u, 700)) + [1, 2, 3, 5, 8]
+    for p, q in ((3, 3), (3, 2), (4, 3)):
+        want = oracle.count_ranks(g, p, q, ranks, anchor="U", order_key=oracle.ORDER_DEGREE,
+                                  max_nodes=20_000_000)
+        done = [(r, w) for r, w in zip(ranks, want) if w is not None]
+        assert len(done) >= len(ranks) // 2
+        for r, w in done:
+            assert bc.bc_count_roots(G, p, q, 0, r, r + 1) == w, ((p, q), r)
+        # the same roots in one call (consecutive roots share a block's range hint)
+        lo, hi = 0, 1200
+        want_run = oracle.count_ranks(g, p, q, list(range(lo, hi)), anchor="U", order_key=oracle.ORDER_DEGREE)
+        assert bc.bc_count_roots(G, p, q, 0, lo, hi) == sum(want_run)
+        say("hubs per-root", (p, q), len(done), "of", len(ranks))
