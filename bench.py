@@ -29,9 +29,9 @@ OPS_PER_WORD_PAIR = 2 * 64
 # HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
 # 1 GiB device copy), valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256_PREFIX = "174d3ac36c929cf3"
+TRAFFIC_KERNEL_SHA256_PREFIX = "88eeb9a15fa29ad1"
 TRAFFIC_WORKLOAD = "power_law_2m"
-TRAFFIC_BYTES_Q44 = (1190382 * 2.0 + 5578662 * 1.0) * 1024
+TRAFFIC_BYTES_Q44 = (1187827.3125 * 2.0 + 5565581.375 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4)]),
