@@ -57,7 +57,13 @@ typedef struct {
 
 typedef struct bc_graph bc_graph;   /* opaque; immutable after bc_build */
 
-/* Anchor: the side that L is drawn from.  The count never depends on it. */
+/* Anchor: the side that L is drawn from.  The count never depends on it.
+ * AUTO takes the side with the smaller of p, q as L's (U when p < q, V when
+ * q < p, U when p == q <= 2).  For p == q >= 3 it takes the side with the
+ * smaller planning cost (sum over roots of k^min(p-1,3) times the root's row
+ * words, k = the root's candidates): estimated from 1 in 16 roots of each side
+ * when the two sides have at least 65536 roots together and the estimates differ
+ * by more than 15 %, otherwise from a candidate pass over all roots of both. */
 enum { BC_ANCHOR_AUTO = -1, BC_ANCHOR_U = 0, BC_ANCHOR_V = 1 };
 
 /* Options.  Pass NULL for all defaults.  No field changes any count. */

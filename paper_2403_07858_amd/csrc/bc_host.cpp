@@ -496,6 +496,7 @@ struct HostJob {
     uint32_t pA, qA;
     uint32_t root_lo, root_hi;
     bool trivial_zero;
+    bool dropped;              // the other anchor of its spec was chosen from a sample
     uint64_t cost;             // planning proxy after the candidate pass
     uint64_t weight;           // the same over the whole depth (job ordering)
 };
@@ -603,7 +604,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     unsigned long long *d_queue;
     BC_HIP(mem.get(&d_jobs, nj));
     BC_HIP(mem.get(&d_tab, tab_off[nj]));
-    BC_HIP(mem.get(&d_slots, nj));
+    BC_HIP(mem.get(&d_slots, nj + 1));   // slot nj: sample jobs
     BC_HIP(mem.get(&d_queue, 8));
     {
         std::vector<u128> tab(tab_off[nj]);
@@ -615,7 +616,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         BC_HIP(hipMemcpyAsync(d_jobs, hjobs.data(), nj * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
         BC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
     }
-    BC_HIP(bcdev::launch_fill_slots(d_slots, nj, st));
+    BC_HIP(bcdev::launch_fill_slots(d_slots, nj + 1, st));
     BC_HIP(fill_u32((uint32_t *)d_queue, 16, 0u, st));
 
     Timer tm;
@@ -632,12 +633,110 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         BC_HIP(bcdev::launch_degree_sum(d_jobs, d_ids, (uint32_t)deg_jobs.size(), d_slots, st));
     }
 
-    // 4. Candidate pass over all roots of jobs with pA >= 2.
+    // The fused per-root kernel (LDS counting, rows bump-allocated on the
+    // device) needs 144 KiB of LDS per block and a pool sized up front; the
+    // two-kernel path (count, plan, rows) is the fallback.
+    const bool fused = lds_per_block(device) >= 148 * 1024;
+    bcdev::RootScratch rs{};
+    uint32_t rs_blocks = 0;
+
+    // 4a. Specs with both anchors as candidates: estimate each side's
+    //     planning cost from a rank-stratified sample of its roots
+    //     (kSampleChunk consecutive ranks out of every kSamplePeriod), counted
+    //     as candidate-only jobs (p_A = 2, spare slot), and drop a side that is
+    //     dearer by more than the margin; close calls take both full passes.
+    if (fused) {
+        constexpr uint32_t kSampleChunk = 16, kSamplePeriod = 256;
+        constexpr uint64_t kSampleMinRoots = 65536;
+        constexpr double kSampleMargin = 1.15;
+        std::vector<bcdev::Job> sjobs;
+        std::vector<uint32_t> sowner;            // jobs[] index of each sample job
+        std::vector<uint64_t> sprefix(1, 0);
+        for (size_t i = 0; i < ns; ++i) {
+            if (spec_jobs[i].size() != 2) continue;
+            const int a = spec_jobs[i][0], b = spec_jobs[i][1];
+            if (jobs[a].trivial_zero || jobs[b].trivial_zero || jobs[a].pA < 3 || jobs[b].pA < 3) continue;
+            const uint64_t span = (uint64_t)(jobs[a].root_hi - jobs[a].root_lo) + (jobs[b].root_hi - jobs[b].root_lo);
+            if (span < kSampleMinRoots) continue;
+            for (int j : {a, b}) {
+                for (uint64_t c = jobs[j].root_lo; c < jobs[j].root_hi; c += kSamplePeriod) {
+                    bcdev::Job sj = hjobs[j];
+                    sj.root_lo = (uint32_t)c;
+                    sj.root_hi = (uint32_t)std::min<uint64_t>(c + kSampleChunk, jobs[j].root_hi);
+                    sj.pA = 2;
+                    sj.slot = nj;
+                    sjobs.push_back(sj);
+                    sowner.push_back((uint32_t)j);
+                    sprefix.push_back(sprefix.back() + (sj.root_hi - sj.root_lo));
+                }
+            }
+        }
+        if (!sjobs.empty()) {
+            // the counter scratch is sized for any later pass too
+            uint32_t nA_all = 1;
+            for (uint32_t j = 0; j < nj; ++j)
+                if (!jobs[j].trivial_zero && jobs[j].pA >= 2) nA_all = std::max(nA_all, hjobs[j].nA);
+            rs_blocks = (uint32_t)ncu * 2;
+            rs.stride = nA_all;
+            BC_HIP(mem.get(&rs.cnt, (uint64_t)rs_blocks * nA_all));
+            BC_HIP(mem.get(&rs.touched, (uint64_t)rs_blocks * nA_all));
+            BC_HIP(mem.get(&rs.cand, (uint64_t)rs_blocks * nA_all));
+            BC_HIP(fill_u32(rs.cnt, (uint64_t)rs_blocks * nA_all, 0u, st));
+            const uint64_t s_roots = sprefix.back();
+            bcdev::Job *d_sj;
+            uint64_t *d_sp, *d_soff, *d_spool;
+            uint32_t *d_sk;
+            BC_HIP(mem.get(&d_sj, sjobs.size()));
+            BC_HIP(mem.get(&d_sp, sprefix.size()));
+            BC_HIP(mem.get(&d_sk, s_roots));
+            BC_HIP(mem.get(&d_soff, s_roots));
+            BC_HIP(mem.get(&d_spool, 1));
+            BC_HIP(hipMemcpyAsync(d_sj, sjobs.data(), sjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
+            BC_HIP(hipMemcpyAsync(d_sp, sprefix.data(), sprefix.size() * 8, hipMemcpyHostToDevice, st));
+            const uint32_t s_blocks = (uint32_t)std::min<uint64_t>(
+                s_roots, std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
+            BC_HIP(bcdev::launch_root_build(d_sj, d_sp, (uint32_t)sjobs.size(), s_roots, rs, d_spool, 1, s_blocks,
+                                            d_queue + 6, d_sk, d_soff, d_slots, st));
+            std::vector<uint32_t> sk(s_roots);
+            BC_HIP(hipMemcpyAsync(sk.data(), d_sk, s_roots * 4, hipMemcpyDeviceToHost, st));
+            BC_HIP(hipStreamSynchronize(st));
+            std::vector<double> est(nj, 0.0), seen(nj, 0.0);
+            for (size_t s = 0; s < sjobs.size(); ++s) {
+                const uint32_t j = sowner[s];
+                const Side &A = specs[jobs[j].spec].g->side[jobs[j].anchor];
+                const uint32_t e = std::min<uint32_t>(jobs[j].pA - 1, 3);
+                for (uint64_t r = sprefix[s]; r < sprefix[s + 1]; ++r) {
+                    const double k = sk[r];
+                    const uint64_t u = sjobs[s].root_lo + (r - sprefix[s]);
+                    seen[j] += 1.0;
+                    if (k < jobs[j].pA - 1) continue;
+                    double x = k * (double)((A.h_ptr[u + 1] - A.h_ptr[u] + 63) / 64);
+                    for (uint32_t t = 1; t < e; ++t) x *= k;
+                    est[j] += x;
+                }
+            }
+            for (size_t i = 0; i < ns; ++i) {
+                if (spec_jobs[i].size() != 2) continue;
+                const int a = spec_jobs[i][0], b = spec_jobs[i][1];
+                if (seen[a] == 0.0 || seen[b] == 0.0) continue;
+                const double ca = est[a] * (jobs[a].root_hi - jobs[a].root_lo) / seen[a];
+                const double cb = est[b] * (jobs[b].root_hi - jobs[b].root_lo) / seen[b];
+                int drop = -1;
+                if (ca * kSampleMargin < cb) drop = b;
+                else if (cb * kSampleMargin < ca) drop = a;
+                if (drop < 0) continue;
+                jobs[drop].dropped = true;
+                spec_jobs[i] = {drop == a ? b : a};
+            }
+        }
+    }
+
+    // 4b. Candidate pass over all roots of jobs with pA >= 2.
     std::vector<uint32_t> cj;   // jobs in the candidate pass
     std::vector<uint64_t> root_prefix(1, 0);
     uint32_t nA_max = 1;
     for (uint32_t j = 0; j < nj; ++j)
-        if (!jobs[j].trivial_zero && jobs[j].pA >= 2) cj.push_back(j);
+        if (!jobs[j].trivial_zero && !jobs[j].dropped && jobs[j].pA >= 2) cj.push_back(j);
     if (short_first)   // served batches: the small graphs' candidate passes first
         std::stable_sort(cj.begin(), cj.end(), [&](uint32_t a, uint32_t b) {
             return specs[jobs[a].spec].g->nnz < specs[jobs[b].spec].g->nnz;
@@ -649,14 +748,9 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     const uint64_t total_roots = root_prefix.back();
     std::vector<uint32_t> h_k(total_roots);
     std::vector<uint64_t> h_off;
-    bcdev::RootScratch rs{};
     const uint32_t root_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(total_roots, 1), (uint64_t)ncu * 2);
     std::vector<bcdev::Job> cjobs;
     bcdev::Job *d_cjobs = nullptr;
-    // The fused per-root kernel (LDS counting, rows bump-allocated on the
-    // device) needs 144 KiB of LDS per block and a pool sized up front; the
-    // two-kernel path (count, plan, rows) is the fallback.
-    const bool fused = lds_per_block(device) >= 148 * 1024;
     uint64_t *d_pool_fused = nullptr;
     uint64_t pool_cap = 0;
     if (total_roots) {
@@ -668,11 +762,13 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         BC_HIP(mem.get(&d_cjobs, cjobs.size()));
         BC_HIP(mem.get(&d_rp, root_prefix.size()));
         BC_HIP(mem.get(&d_k, total_roots));
-        rs.stride = nA_max;
-        BC_HIP(mem.get(&rs.cnt, (uint64_t)root_blocks * nA_max));
-        BC_HIP(mem.get(&rs.touched, (uint64_t)root_blocks * nA_max));
-        BC_HIP(mem.get(&rs.cand, (uint64_t)root_blocks * nA_max));
-        BC_HIP(fill_u32(rs.cnt, (uint64_t)root_blocks * nA_max, 0u, st));
+        if (rs_blocks == 0) {   // else the sample pass sized it for every pass (left all zero)
+            rs.stride = nA_max;
+            BC_HIP(mem.get(&rs.cnt, (uint64_t)root_blocks * nA_max));
+            BC_HIP(mem.get(&rs.touched, (uint64_t)root_blocks * nA_max));
+            BC_HIP(mem.get(&rs.cand, (uint64_t)root_blocks * nA_max));
+            BC_HIP(fill_u32(rs.cnt, (uint64_t)root_blocks * nA_max, 0u, st));
+        }
         BC_HIP(hipMemcpyAsync(d_cjobs, cjobs.data(), cjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
         BC_HIP(hipMemcpyAsync(d_rp, root_prefix.data(), root_prefix.size() * 8, hipMemcpyHostToDevice, st));
         if (fused) {
