@@ -31,7 +31,7 @@ OPS_PER_WORD_PAIR = 2 * 64
 # 1 GiB device copy), valid only for the kernel source they were taken on.
 TRAFFIC_KERNEL_SHA256_PREFIX = "88eeb9a15fa29ad1"
 TRAFFIC_WORKLOAD = "power_law_2m"
-TRAFFIC_BYTES_Q44 = (1187827.3125 * 2.0 + 5565581.375 * 1.0) * 1024
+TRAFFIC_BYTES_Q44 = (1180998.8125 * 2.0 + 5472978.78125 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4)]),
