@@ -501,6 +501,37 @@ struct HostJob {
     uint64_t weight;           // the same over the whole depth (job ordering)
 };
 
+// Positions of cost[] in descending cost order, equal costs in ascending
+// position (the order a stable sort gives): LSD radix sort over 8-bit digits
+// of the complemented key, skipping digits on which all keys agree.
+std::vector<uint32_t> order_by_cost_desc(const std::vector<uint64_t> &cost)
+{
+    const size_t n = cost.size();
+    std::vector<uint32_t> a(n), b(n);
+    std::vector<uint64_t> key(n), kb(n);
+    std::iota(a.begin(), a.end(), 0u);
+    uint64_t any = 0, all = ~0ull;
+    for (size_t i = 0; i < n; ++i) {
+        key[i] = ~cost[i];
+        any |= key[i];
+        all &= key[i];
+    }
+    for (int sh = 0; sh < 64; sh += 8) {
+        if ((((any ^ all) >> sh) & 0xff) == 0) continue;
+        size_t cnt[257] = {0};
+        for (size_t i = 0; i < n; ++i) ++cnt[((key[i] >> sh) & 0xff) + 1];
+        for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
+        for (size_t i = 0; i < n; ++i) {
+            const size_t o = cnt[(key[i] >> sh) & 0xff]++;
+            b[o] = a[i];
+            kb[o] = key[i];
+        }
+        a.swap(b);
+        key.swap(kb);
+    }
+    return a;
+}
+
 // short_first: order the tasks job by job, cheapest job (by the cost proxy)
 // first, instead of all tasks by cost -- for served batches, where one job
 // that cannot meet its deadline must not hold back the others.
@@ -860,8 +891,14 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             if (a.c != b.c) return a.c < b.c;
             return a.cost > b.cost;
         });
-    else
-        std::stable_sort(plan.begin(), plan.end(), [](const Plan &a, const Plan &b) { return a.cost > b.cost; });
+    else {
+        std::vector<uint64_t> cost(plan.size());
+        for (size_t r = 0; r < plan.size(); ++r) cost[r] = plan[r].cost;
+        const std::vector<uint32_t> ord = order_by_cost_desc(cost);
+        std::vector<Plan> sorted(plan.size());
+        for (size_t r = 0; r < plan.size(); ++r) sorted[r] = plan[ord[r]];
+        plan.swap(sorted);
+    }
     std::vector<bcdev::ActiveRoot> aroots(plan.size());
     uint64_t pool_words = 0, tasks = 0, slab_need = 64;
     // rows already built by the fused kernel, unless some root found no room
