@@ -61,9 +61,11 @@ typedef struct bc_graph bc_graph;   /* opaque; immutable after bc_build */
  * AUTO takes the side with the smaller of p, q as L's (U when p < q, V when
  * q < p, U when p == q <= 2).  For p == q >= 3 it takes the side with the
  * smaller planning cost (sum over roots of k^min(p-1,3) times the root's row
- * words, k = the root's candidates): estimated from 1 in 16 roots of each side
- * when the two sides have at least 65536 roots together and the estimates differ
- * by more than 15 %, otherwise from a candidate pass over all roots of both. */
+ * words, k = the root's candidates).  When the two sides have at least 65536
+ * roots together it is estimated from 1 in 16 roots of each side; estimates
+ * within 15 % of each other go to the side whose candidate pass scans fewer
+ * wedges (sum over the other side's vertices of C(d,2)).  Smaller graphs take
+ * the cost from a candidate pass over all roots of both sides. */
 enum { BC_ANCHOR_AUTO = -1, BC_ANCHOR_U = 0, BC_ANCHOR_V = 1 };
 
 /* Options.  Pass NULL for all defaults.  No field changes any count. */

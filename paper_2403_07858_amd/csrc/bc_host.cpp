@@ -70,6 +70,8 @@ void parallel_for(uint64_t n, F f)
 struct Side {
     uint64_t n = 0;
     uint32_t max_deg = 0;
+    double deg_pairs = 0;            // sum over the side's vertices of C(d, 2): the wedges that
+                                     // a candidate pass anchored on the other side scans
     std::vector<uint32_t> rank_of;   // original id -> rank
     std::vector<uint64_t> h_ptr;     // relabelled CSR on the host (by rank)
     uint64_t *d_ptr = nullptr;
@@ -239,8 +241,11 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
         Side &sd = g->side[s];
         sd.n = cs[s]->n_rows;
         relabel(cs[s], *rows[s], *ids[s], g->side[1 - s].rank_of, sd.h_ptr, adj[s]);
-        for (uint64_t r = 0; r < sd.n; ++r)
-            sd.max_deg = std::max<uint32_t>(sd.max_deg, (uint32_t)(sd.h_ptr[r + 1] - sd.h_ptr[r]));
+        for (uint64_t r = 0; r < sd.n; ++r) {
+            const uint64_t d = sd.h_ptr[r + 1] - sd.h_ptr[r];
+            sd.max_deg = std::max<uint32_t>(sd.max_deg, (uint32_t)d);
+            sd.deg_pairs += 0.5 * (double)d * (double)(d ? d - 1 : 0);
+        }
     }
     // Reverse positions: for the edge (a, b) stored in a's row, the index of a
     // within b's row.  Visiting b in increasing order meets a's edges in the
@@ -675,7 +680,8 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     //     planning cost from a rank-stratified sample of its roots
     //     (kSampleChunk consecutive ranks out of every kSamplePeriod), counted
     //     as candidate-only jobs (p_A = 2, spare slot), and drop a side that is
-    //     dearer by more than the margin; close calls take both full passes.
+    //     dearer by more than the margin.  Within the margin the side whose
+    //     candidate pass scans fewer wedges is kept.
     if (fused) {
         constexpr uint32_t kSampleChunk = 16, kSamplePeriod = 256;
         constexpr uint64_t kSampleMinRoots = 65536;
@@ -752,10 +758,14 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
                 if (seen[a] == 0.0 || seen[b] == 0.0) continue;
                 const double ca = est[a] * (jobs[a].root_hi - jobs[a].root_lo) / seen[a];
                 const double cb = est[b] * (jobs[b].root_hi - jobs[b].root_lo) / seen[b];
-                int drop = -1;
+                int drop;
                 if (ca * kSampleMargin < cb) drop = b;
                 else if (cb * kSampleMargin < ca) drop = a;
-                if (drop < 0) continue;
+                else {
+                    // a wedge u - v - w of anchor A passes through v on the other side
+                    const bc_graph *g = specs[i].g;
+                    drop = g->side[1 - jobs[a].anchor].deg_pairs <= g->side[1 - jobs[b].anchor].deg_pairs ? b : a;
+                }
                 jobs[drop].dropped = true;
                 spec_jobs[i] = {drop == a ? b : a};
             }
