@@ -80,6 +80,7 @@ struct EnumParams {
     const Job *jobs;
     const ActiveRoot *roots;
     uint32_t n_roots;
+    uint32_t task_chunk;    // consecutive tasks taken per queue pop (>= 1)
     uint64_t n_tasks;
     const uint64_t *pool;
     uint64_t *slab;         // per-wave global scratch

@@ -965,6 +965,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         prm.roots = d_roots;
         prm.n_roots = (uint32_t)aroots.size();
         prm.n_tasks = tasks;
+        // launches with many tasks per wave take them 8 at a time (fewer
+        // queue atomics and root searches; consecutive tasks share their
+        // root's rows), small ones 4 at a time (a more even spread)
+        prm.task_chunk = tasks >= 1024ull * blocks * bcdev::kWavesPerBlock ? 8u : 4u;
         prm.pool = d_pool;
         prm.slab = d_slab;
         prm.slab_words = slab_need;

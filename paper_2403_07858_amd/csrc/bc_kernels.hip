@@ -30,7 +30,6 @@ constexpr uint32_t kLdsWordsPerWave = 600;    // LDS arena per wavefront (64-bit
 constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of the tiled leaf sum
 constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
-constexpr uint32_t kTaskChunk = 4;            // consecutive tasks taken per queue pop
 constexpr uint32_t kFilterDepth = 4;          // 64-row chunks loaded at once by the level-2 filter
 constexpr uint32_t kTripleRows = 96;          // nodes up to this many rows finish their last three levels at once
 
@@ -2013,13 +2012,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     Counters ct{};
     uint32_t cur_job = 0xffffffffu;
     for (;;) {
-        // pop kTaskChunk consecutive tasks; only the first needs the root
+        // pop task_chunk consecutive tasks; only the first needs the root
         // search, the rest advance through the (contiguous) task ranges
         unsigned long long t0 = 0;
-        if (ln == 0) t0 = atomicAdd(prm.queue, (unsigned long long)kTaskChunk);
+        if (ln == 0) t0 = atomicAdd(prm.queue, (unsigned long long)prm.task_chunk);
         t0 = bcast64(t0, 0);
         if (t0 >= prm.n_tasks) break;
-        const unsigned long long t_end = min(t0 + kTaskChunk, (unsigned long long)prm.n_tasks);
+        const unsigned long long t_end = min(t0 + prm.task_chunk, (unsigned long long)prm.n_tasks);
         // root owning task t0: largest r with roots[r].task_begin <= t0
         uint32_t r = 0, hi = prm.n_roots;
         while (hi - r > 1) {
