@@ -29,9 +29,9 @@ OPS_PER_WORD_PAIR = 2 * 64
 # HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
 # 1 GiB device copy), valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256_PREFIX = "88eeb9a15fa29ad1"
+TRAFFIC_KERNEL_SHA256_PREFIX = "95d1750a23bec4b4"
 TRAFFIC_WORKLOAD = "power_law_2m"
-TRAFFIC_BYTES_Q44 = (1180998.8125 * 2.0 + 5472978.78125 * 1.0) * 1024
+TRAFFIC_BYTES_Q44 = (1156403.0625 * 2.0 + 6162921.90625 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4)]),
