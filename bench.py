@@ -75,7 +75,7 @@ def main():
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the count is additive over root ranges; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
