@@ -68,7 +68,37 @@ typedef struct bc_graph bc_graph;   /* opaque; immutable after bc_build */
  * the cost from a candidate pass over all roots of both sides. */
 enum { BC_ANCHOR_AUTO = -1, BC_ANCHOR_U = 0, BC_ANCHOR_V = 1 };
 
-/* Options.  Pass NULL for all defaults.  No field changes any count. */
+/*
+ * Device-memory hook (e.g. a framework's caching allocator).  alloc returns
+ * `bytes` of device memory usable by work queued on `stream` (a hipStream_t),
+ * or NULL when it cannot (the call then fails with BC_E_OOM after releasing
+ * everything it took).  free gives back a block alloc returned; the library
+ * calls it with the same stream once all work it queued on the block is on
+ * that stream, so a stream-ordered allocator may reuse the block at once.
+ * Blocks a graph keeps (bc_build) are freed by bc_free with stream NULL.
+ * The hook object and ctx must outlive every call and graph that uses them.
+ */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+} bc_allocator;
+
+/* Vertex order keys of bc_build (Definition 2: vertex priority). */
+enum {
+    BC_ORDER_DEGREE = 0,    /* ascending degree, ties by id (default) */
+    BC_ORDER_TWO_HOP = 1    /* ascending |N_2^k(x)|: same-side vertices sharing >= k neighbours with x,
+                               k = bc_opts.order_k (0 = 2); ties by original id */
+};
+
+/* Root-build paths (bc_opts.root_build). */
+enum {
+    BC_ROOT_BUILD_AUTO = 0,      /* one fused kernel per root (LDS hash table) when the device has the LDS */
+    BC_ROOT_BUILD_TWO_PASS = 1   /* candidate counts, host plan, then rows: two kernels with HBM counters */
+};
+
+/* Options.  Pass NULL for all defaults.  No field changes any count.
+ * Fields after timeout_ms are read only when struct_size covers them. */
 typedef struct {
     uint32_t struct_size;      /* sizeof(bc_opts), for forward compatibility */
     void *stream;              /* hipStream_t to run on; NULL = the library's own stream */
@@ -79,6 +109,20 @@ typedef struct {
     uint32_t instrument;       /* nonzero: fill the work counters of bc_stats */
     uint32_t timeout_ms;       /* device-side time limit of the call (0 = none); past it the
                                   call fails with BC_E_TIMEOUT and no count is returned */
+    const bc_allocator *alloc; /* device memory for the call's scratch (and, in bc_build, the
+                                  graph's arrays); NULL = hipMallocAsync on the stream */
+    int32_t order_key;         /* bc_build: BC_ORDER_DEGREE or BC_ORDER_TWO_HOP */
+    uint32_t order_k;          /* bc_build, BC_ORDER_TWO_HOP: the sharing threshold k (0 = 2) */
+    uint32_t roots_per_wave;   /* enumeration tasks a wavefront takes per queue pop, 1..64;
+                                  0 = auto (8 on launches with >= 1024 tasks per wave, else 4) */
+    uint32_t switch_depth;     /* levels above the leaves that a small node expands breadth-first in
+                                  one matrix-core sweep instead of depth-first: 2 (pairs of the last
+                                  candidate list) or 3 (triples, nodes of <= 96 rows); 0 = auto (3) */
+    uint32_t split_rows;       /* runtime split of heavy tasks (p_A >= 5): a (root, second vertex)
+                                  task whose level-2 block keeps more rows than this pushes one
+                                  subtask per row to a device queue that idle wavefronts drain;
+                                  0 = auto (256), 0xffffffff = never split */
+    uint32_t root_build;       /* BC_ROOT_BUILD_AUTO / _TWO_PASS */
 } bc_opts;
 
 /* Timings (milliseconds, measured with HIP events on the stream) and work
@@ -106,11 +150,13 @@ typedef struct {
  *
  * U lists N(u) for every u in U (n_rows = |U|, n_cols = |V|); V lists N(v)
  * for every v in V and must be the exact transpose of U (BC_E_INCONSISTENT
- * otherwise).  Rows are sorted and each side is relabelled by degree order
- * (ascending degree, ties by original id); a vertex's position in that order
- * is its "rank", which fixes the orientation of the search (vertex priority,
- * Section III-B, Definition 2 with degree as the key).  Both CSR sides are
- * then copied to device memory on opts->stream.  The caller keeps ownership
+ * otherwise).  Rows are sorted and each side is relabelled by its vertex
+ * order: ascending degree, ties by original id (BC_ORDER_DEGREE), or
+ * ascending |N_2^k| (BC_ORDER_TWO_HOP, Definition 2's priority, computed on
+ * the host by wedge counting).  A vertex's position in that order is its
+ * "rank", which fixes the orientation of the search (vertex priority,
+ * Section III-B).  Both CSR sides are then copied to device memory on
+ * opts->stream (through opts->alloc when given).  The caller keeps ownership
  * of its arrays; nothing refers to them after return.  *out receives a graph
  * that owns its device memory until bc_free.
  */
@@ -133,9 +179,13 @@ bc_status bc_ranks(const bc_graph *g, int32_t side, uint32_t *rank_of);
  *
  * Runs entirely on the device (Algorithm 1 restated for CDNA4): per-root
  * 2-hop candidate collection, bitmap rows of the common neighbours,
- * enumeration with AND + popcount, each leaf adding C(|S|, q) from an exact
- * table.  p > |U| or q > |V| gives 0.  The call returns when the count is on
- * the host.  *st (nullable) receives timings and counters.
+ * enumeration whose child filters are AND + popcount on the vector units,
+ * and leaves adding C(|S|, q) from an exact table.  The leaf intersection
+ * sizes of a candidate list come, pair by pair, from an int8 product of its
+ * 0/1 rows on the matrix cores when every leaf value is below 2^28 (exact
+ * integer arithmetic), else from AND + popcount.  p > |U| or q > |V| gives
+ * 0.  The call returns when the count is on the host.  *st (nullable)
+ * receives timings and counters.
  */
 bc_status bc_count(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts,
                    bc_u128 *out, bc_stats *st);
@@ -153,10 +203,16 @@ bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, int32_t anch
 /*
  * bc_count_batch -- n independent counts (graphs[i], p[i], q[i]) in one set
  * of persistent launches sharing one task queue.  out[i] and item_status[i]
- * receive each result; the call itself fails only on argument or device
- * errors.  Every out[i] equals what bc_count would return.  st (nullable)
- * receives the timings of the whole call and work counters summed over all
- * items (anchor: that of the first item).
+ * receive each result; every out[i] with item_status[i] == BC_OK equals what
+ * bc_count would return (out[i] is 0 otherwise).  Items with a bad graph
+ * pointer or p, q outside 1..32 get BC_E_INVALID_ARG and the rest still run.
+ * When the call as a whole fails before the counts are read back (device
+ * error, BC_E_OOM, ...), it returns that status and every item that was to
+ * run gets the same status: no item reports BC_OK unless its count was
+ * computed.  BC_E_DEVICE with per-item statuses is also returned when an
+ * item hit an internal bound.  st (nullable) receives the timings of the
+ * whole call and work counters summed over all items (anchor: that of the
+ * first item).
  */
 bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q,
                          size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st);

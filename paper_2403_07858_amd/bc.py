@@ -32,6 +32,8 @@ BC_E_PENDING = -10
 BC_E_NOT_FOUND = -11
 
 BC_ANCHOR_AUTO, BC_ANCHOR_U, BC_ANCHOR_V = -1, 0, 1
+BC_ORDER_DEGREE, BC_ORDER_TWO_HOP = 0, 1
+BC_ROOT_BUILD_AUTO, BC_ROOT_BUILD_TWO_PASS = 0, 1
 
 
 class bc_u128(ctypes.Structure):
@@ -47,10 +49,55 @@ class bc_csr(ctypes.Structure):
                 ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class bc_allocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
 class bc_opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("stream", ctypes.c_void_p), ("anchor", ctypes.c_int32),
                 ("lds_words", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
-                ("instrument", ctypes.c_uint32), ("timeout_ms", ctypes.c_uint32)]
+                ("instrument", ctypes.c_uint32), ("timeout_ms", ctypes.c_uint32),
+                ("alloc", ctypes.POINTER(bc_allocator)), ("order_key", ctypes.c_int32),
+                ("order_k", ctypes.c_uint32), ("roots_per_wave", ctypes.c_uint32),
+                ("switch_depth", ctypes.c_uint32), ("split_rows", ctypes.c_uint32),
+                ("root_build", ctypes.c_uint32)]
+
+
+class Allocator:
+    """A ``bc_allocator`` made of two Python callables: ``alloc(nbytes, stream)``
+    returns a device pointer (int; 0 or None when it cannot) and
+    ``free(ptr, stream)`` gives it back.  Keep the object alive while any call
+    or graph uses it."""
+
+    def __init__(self, alloc, free):
+        def _a(_ctx, n, st):
+            try:
+                return alloc(int(n), int(st or 0)) or None
+            except Exception:   # a raising hook is an allocation failure
+                return None
+
+        def _f(_ctx, ptr, st):
+            try:
+                free(int(ptr), int(st or 0))
+            except Exception:
+                pass
+
+        self._a, self._f = _ALLOC_FN(_a), _FREE_FN(_f)
+        self.struct = bc_allocator(None, self._a, self._f)
+
+
+def torch_allocator(device=None) -> Allocator:
+    """Device memory from torch's caching allocator (stream-ordered on the
+    stream the library passes)."""
+    import torch
+
+    dev = torch.cuda.current_device() if device is None else device
+    return Allocator(lambda n, st: torch.cuda.caching_allocator_alloc(n, dev, st),
+                     lambda ptr, st: torch.cuda.caching_allocator_delete(ptr))
 
 
 class bc_stats(ctypes.Structure):
@@ -127,7 +174,8 @@ def _stream_handle(stream):
 
 
 def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, instrument=False,
-              timeout_ms=0) -> bc_opts:
+              timeout_ms=0, allocator=None, order_key=BC_ORDER_DEGREE, order_k=0, roots_per_wave=0,
+              switch_depth=0, split_rows=0, root_build=BC_ROOT_BUILD_AUTO) -> bc_opts:
     o = bc_opts()
     o.struct_size = ctypes.sizeof(bc_opts)
     o.stream = _stream_handle(stream)
@@ -136,6 +184,14 @@ def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, i
     o.waves_per_cu = waves_per_cu
     o.instrument = 1 if instrument else 0
     o.timeout_ms = timeout_ms
+    if allocator is not None:
+        o.alloc = ctypes.pointer(allocator.struct)
+    o.order_key = order_key
+    o.order_k = order_k
+    o.roots_per_wave = roots_per_wave
+    o.switch_depth = switch_depth
+    o.split_rows = split_rows
+    o.root_build = root_build
     return o
 
 
@@ -153,9 +209,10 @@ def _csr(n_rows, n_cols, indptr, indices, keep):
 class Graph:
     """A graph resident on the device (owns a ``bc_graph *``)."""
 
-    def __init__(self, handle: int, n_u: int, n_v: int, n_edges: int):
+    def __init__(self, handle: int, n_u: int, n_v: int, n_edges: int, allocator=None):
         self.handle = handle
         self.n_u, self.n_v, self.n_edges = n_u, n_v, n_edges
+        self._allocator = allocator   # a hook the graph's arrays came from must outlive them
 
     def close(self):
         if self.handle:
@@ -179,7 +236,7 @@ def bc_build(n_u, n_v, indptr_u, indices_u, indptr_v, indices_v, **opt) -> Graph
     s = _lib.bc_build(ctypes.byref(cu), ctypes.byref(cv), ctypes.byref(o), ctypes.byref(h))
     if s != BC_OK:
         raise BCError(s, "bc_build")
-    return Graph(h.value, n_u, n_v, cu.nnz)
+    return Graph(h.value, n_u, n_v, cu.nnz, opt.get("allocator"))
 
 
 def build_graph(g, **opt) -> Graph:

@@ -87,6 +87,8 @@ struct EnumParams {
     uint64_t slab_words;    // words per wave
     uint32_t lds_words;     // per-wave LDS words actually used (<= compiled cap)
     uint32_t instrument;
+    uint32_t triple;        // nonzero: small nodes three levels above the leaves take the triple sweep
+    uint32_t split_rows;    // level-2 blocks with more rows are split into queued subtasks (0 = default)
     unsigned long long *queue;   // task counter
     Slot *slots;
 };

@@ -4,6 +4,7 @@
 #include "bc.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstddef>
 #include <chrono>
 #include <cstdio>
@@ -29,9 +30,11 @@ bc_status set_error(bc_status s, const std::string &msg)
     return s;
 }
 
+// A failed HIP call: out of device memory is BC_E_OOM, anything else BC_E_DEVICE.
 bc_status hip_error(hipError_t e, const char *what)
 {
-    return set_error(BC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return set_error(e == hipErrorOutOfMemory ? BC_E_OOM : BC_E_DEVICE,
+                     std::string(what) + ": " + hipGetErrorString(e));
 }
 
 #define BC_HIP(call)                                             \
@@ -85,6 +88,8 @@ struct bc_graph {
     Side side[2];
     uint64_t nnz = 0;
     int device = 0;
+    bool hooked = false;       // device arrays came from `hook` (freed through it)
+    bc_allocator hook{};
 };
 
 namespace {
@@ -104,12 +109,29 @@ hipStream_t pick_stream(const bc_opts *o)
     return own_stream();
 }
 
+// Value of an option field, or dflt when opts is NULL or struct_size does not
+// cover the field (callers built against an older, shorter bc_opts).
+#define BC_OPT(o, field, dflt) \
+    (((o) && (o)->struct_size >= offsetof(bc_opts, field) + sizeof((o)->field)) ? (o)->field : (dflt))
+
 bc_status check_opts(const bc_opts *o)
 {
     if (!o) return BC_OK;
     if (o->struct_size != 0 && o->struct_size < sizeof(uint32_t) * 2)
         return set_error(BC_E_INVALID_ARG, "bc_opts.struct_size too small");
     if (o->anchor < -1 || o->anchor > 1) return set_error(BC_E_INVALID_ARG, "bc_opts.anchor must be -1, 0 or 1");
+    const bc_allocator *al = BC_OPT(o, alloc, (const bc_allocator *)nullptr);
+    if (al && (!al->alloc || !al->free))
+        return set_error(BC_E_INVALID_ARG, "bc_opts.alloc needs both alloc and free");
+    const int32_t ok = BC_OPT(o, order_key, (int32_t)BC_ORDER_DEGREE);
+    if (ok != BC_ORDER_DEGREE && ok != BC_ORDER_TWO_HOP)
+        return set_error(BC_E_INVALID_ARG, "bc_opts.order_key must be BC_ORDER_DEGREE or BC_ORDER_TWO_HOP");
+    if (BC_OPT(o, roots_per_wave, 0u) > 64) return set_error(BC_E_INVALID_ARG, "bc_opts.roots_per_wave must be 0..64");
+    const uint32_t sd = BC_OPT(o, switch_depth, 0u);
+    if (sd != 0 && sd != 2 && sd != 3) return set_error(BC_E_INVALID_ARG, "bc_opts.switch_depth must be 0, 2 or 3");
+    const uint32_t rb = BC_OPT(o, root_build, 0u);
+    if (rb != BC_ROOT_BUILD_AUTO && rb != BC_ROOT_BUILD_TWO_PASS)
+        return set_error(BC_E_INVALID_ARG, "bc_opts.root_build must be BC_ROOT_BUILD_AUTO or _TWO_PASS");
     return BC_OK;
 }
 
@@ -149,17 +171,64 @@ bc_status validate_side(const bc_csr *c, const char *name, std::vector<uint32_t>
     return BC_OK;
 }
 
-// Rank order of one side: ascending degree, ties by original id.
-void degree_order(const bc_csr *c, std::vector<uint32_t> &id_of_rank, std::vector<uint32_t> &rank_of)
+// Rank order of one side: ascending key, ties by original id.
+void key_order(uint64_t n, const std::vector<uint64_t> &key, std::vector<uint32_t> &id_of_rank,
+               std::vector<uint32_t> &rank_of)
 {
-    const uint64_t n = c->n_rows;
     id_of_rank.resize(n);
     std::iota(id_of_rank.begin(), id_of_rank.end(), 0u);
-    std::stable_sort(id_of_rank.begin(), id_of_rank.end(), [&](uint32_t a, uint32_t b) {
-        return (c->indptr[a + 1] - c->indptr[a]) < (c->indptr[b + 1] - c->indptr[b]);
-    });
+    std::stable_sort(id_of_rank.begin(), id_of_rank.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
     rank_of.resize(n);
     for (uint64_t r = 0; r < n; ++r) rank_of[id_of_rank[r]] = (uint32_t)r;
+}
+
+// Degree of every vertex of side c.
+std::vector<uint64_t> degree_key(const bc_csr *c)
+{
+    std::vector<uint64_t> key(c->n_rows);
+    for (uint64_t x = 0; x < c->n_rows; ++x) key[x] = c->indptr[x + 1] - c->indptr[x];
+    return key;
+}
+
+// |N_2^k(x)| for every vertex x of side c (Section II-A, Definition 2): the
+// vertices y != x of the same side with |N(x) n N(y)| >= k, found by counting
+// the wedges x - v - y through the other side's rows (o, sorted in rows_o).
+// Threads take vertices in chunks, each with its own dense counter array.
+std::vector<uint64_t> two_hop_key(const bc_csr *c, const std::vector<uint32_t> &rows_c, const bc_csr *o,
+                                  const std::vector<uint32_t> &rows_o, uint32_t k)
+{
+    const uint64_t n = c->n_rows;
+    std::vector<uint64_t> key(n, 0);
+    const unsigned nt = std::max(1u, std::min<unsigned>(host_threads(), (unsigned)std::max<uint64_t>(1, n / 256)));
+    std::atomic<uint64_t> next{0};
+    auto work = [&] {
+        std::vector<uint32_t> cnt(n, 0), touched;
+        for (;;) {
+            const uint64_t b = next.fetch_add(256), e = std::min(n, b + 256);
+            if (b >= n) break;
+            for (uint64_t x = b; x < e; ++x) {
+                touched.clear();
+                for (uint64_t i = c->indptr[x]; i < c->indptr[x + 1]; ++i) {
+                    const uint32_t v = rows_c[i];
+                    for (uint64_t j = o->indptr[v]; j < o->indptr[v + 1]; ++j) {
+                        const uint32_t y = rows_o[j];
+                        if (y != x && cnt[y]++ == 0) touched.push_back(y);
+                    }
+                }
+                uint64_t size = 0;
+                for (uint32_t y : touched) {
+                    size += cnt[y] >= k;
+                    cnt[y] = 0;
+                }
+                key[x] = size;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+    return key;
 }
 
 // Relabelled CSR: row r is vertex id_of_rank[r]; neighbours mapped through
@@ -184,11 +253,26 @@ void relabel(const bc_csr *c, const std::vector<uint32_t> &sorted_rows, const st
     });
 }
 
-void free_side(Side &s)
+// A graph's device arrays: hipMalloc, or the caller's hook when bc_build had one.
+hipError_t graph_alloc(bc_graph *g, void **p, uint64_t bytes, hipStream_t st)
 {
-    if (s.d_ptr) (void)hipFree(s.d_ptr);
-    if (s.d_adj) (void)hipFree(s.d_adj);
-    if (s.d_rpos) (void)hipFree(s.d_rpos);
+    if (!g->hooked) return hipMalloc(p, bytes);
+    *p = g->hook.alloc(g->hook.ctx, bytes, st);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void graph_release(bc_graph *g, void *p)
+{
+    if (!p) return;
+    if (g->hooked) g->hook.free(g->hook.ctx, p, nullptr);
+    else (void)hipFree(p);
+}
+
+void free_side(bc_graph *g, Side &s)
+{
+    graph_release(g, s.d_ptr);
+    graph_release(g, s.d_adj);
+    graph_release(g, s.d_rpos);
     s.d_ptr = nullptr;
     s.d_adj = nullptr;
     s.d_rpos = nullptr;
@@ -229,9 +313,19 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
     if (!g) return set_error(BC_E_OOM, "bc_build: host allocation failed");
     g->nnz = U->nnz;
     (void)hipGetDevice(&g->device);
+    if (const bc_allocator *al = BC_OPT(opts, alloc, (const bc_allocator *)nullptr)) {
+        g->hooked = true;
+        g->hook = *al;
+    }
     std::vector<uint32_t> idU, idV;
-    degree_order(U, idU, g->side[0].rank_of);
-    degree_order(V, idV, g->side[1].rank_of);
+    if (BC_OPT(opts, order_key, (int32_t)BC_ORDER_DEGREE) == BC_ORDER_TWO_HOP) {
+        const uint32_t k = std::max(1u, BC_OPT(opts, order_k, 0u) ? BC_OPT(opts, order_k, 0u) : 2u);
+        key_order(U->n_rows, two_hop_key(U, rowsU, V, rowsV, k), idU, g->side[0].rank_of);
+        key_order(V->n_rows, two_hop_key(V, rowsV, U, rowsU, k), idV, g->side[1].rank_of);
+    } else {
+        key_order(U->n_rows, degree_key(U), idU, g->side[0].rank_of);
+        key_order(V->n_rows, degree_key(V), idV, g->side[1].rank_of);
+    }
     const bc_csr *cs[2] = {U, V};
     const std::vector<uint32_t> *rows[2] = {&rowsU, &rowsV};
     const std::vector<uint32_t> *ids[2] = {&idU, &idV};
@@ -261,9 +355,9 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
     for (int s = 0; s < 2; ++s) {
         Side &sd = g->side[s];
         const uint64_t m = std::max<uint64_t>(1, g->nnz) * sizeof(uint32_t);
-        hipError_t e = hipMalloc(&sd.d_ptr, (sd.n + 1) * sizeof(uint64_t));
-        if (e == hipSuccess) e = hipMalloc(&sd.d_adj, m);
-        if (e == hipSuccess) e = hipMalloc(&sd.d_rpos, m);
+        hipError_t e = graph_alloc(g, (void **)&sd.d_ptr, (sd.n + 1) * sizeof(uint64_t), st);
+        if (e == hipSuccess) e = graph_alloc(g, (void **)&sd.d_adj, m, st);
+        if (e == hipSuccess) e = graph_alloc(g, (void **)&sd.d_rpos, m, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(sd.d_ptr, sd.h_ptr.data(), (sd.n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess && g->nnz)
@@ -272,8 +366,9 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
             e = hipMemcpyAsync(sd.d_rpos, rpos[s].data(), g->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
-            free_side(g->side[0]);
-            free_side(g->side[1]);
+            (void)hipStreamSynchronize(st);   // no upload may still read a block handed back
+            free_side(g, g->side[0]);
+            free_side(g, g->side[1]);
             delete g;
             return e == hipErrorOutOfMemory ? set_error(BC_E_OOM, "bc_build: device allocation failed")
                                             : hip_error(e, "bc_build: upload");
@@ -286,8 +381,8 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
 extern "C" void bc_free(bc_graph *g)
 {
     if (!g) return;
-    free_side(g->side[0]);
-    free_side(g->side[1]);
+    free_side(g, g->side[0]);
+    free_side(g, g->side[1]);
     delete g;
 }
 
@@ -312,6 +407,64 @@ extern "C" bc_status bc_ranks(const bc_graph *g, int32_t side, uint32_t *rank_of
 // Query execution.
 
 namespace {
+
+// Device scratch of one call, released when the call ends.  Three sources:
+// stream-ordered hipMallocAsync on the call's stream (default), the caller's
+// allocator hook, or a fixed device region carved by bumping an offset (the
+// no-allocation entry point; nothing is allocated or freed).  Every request
+// is rounded up to 256 bytes.  A failed request returns hipErrorOutOfMemory.
+struct DevAlloc {
+    std::vector<void *> ptrs;
+    hipStream_t st;
+    const bc_allocator *hook = nullptr;
+    uint8_t *fixed = nullptr;
+    uint64_t fixed_cap = 0, fixed_used = 0;
+    bool fixed_short = false;    // a request did not fit the fixed region
+    DevAlloc(hipStream_t s, const bc_allocator *h) : st(s), hook(h) {}
+    DevAlloc(hipStream_t s, void *region, uint64_t cap) : st(s), fixed((uint8_t *)region), fixed_cap(cap) {}
+    ~DevAlloc()
+    {
+        for (void *p : ptrs) {
+            if (hook) hook->free(hook->ctx, p, st);
+            else (void)hipFreeAsync(p, st);
+        }
+    }
+    // bytes left in the fixed region (unbounded for the other sources)
+    uint64_t room() const { return fixed ? fixed_cap - fixed_used : ~0ull; }
+    hipError_t raw(void **p, uint64_t bytes)
+    {
+        bytes = (std::max<uint64_t>(bytes, 1) + 255) & ~255ull;
+        *p = nullptr;
+        if (fixed) {
+            if (bytes > fixed_cap - fixed_used) {
+                fixed_short = true;
+                return hipErrorOutOfMemory;
+            }
+            *p = fixed + fixed_used;
+            fixed_used += bytes;
+            return hipSuccess;
+        }
+        void *v = nullptr;
+        if (hook) {
+            v = hook->alloc(hook->ctx, bytes, st);
+            if (!v) return hipErrorOutOfMemory;
+        } else {
+            hipError_t e = hipMallocAsync(&v, bytes, st);
+            if (e != hipSuccess) return e;
+        }
+        ptrs.push_back(v);
+        *p = v;
+        return hipSuccess;
+    }
+    template <typename T>
+    hipError_t get(T **p, uint64_t count)
+    {
+        void *v = nullptr;
+        hipError_t e = raw(&v, count * sizeof(T));
+        *p = (T *)v;
+        return e;
+    }
+};
 
 struct JobSpec {
     const bc_graph *g;
@@ -348,20 +501,16 @@ bool clock_sample(uint64_t *d, hipStream_t st, uint64_t &tick, double &mid, uint
     return e == hipSuccess;
 }
 
-bc_status device_clock(int device, hipStream_t st, ClockCal &out)
+bc_status device_clock(int device, hipStream_t st, DevAlloc &mem, ClockCal &out)
 {
     static std::mutex mu;
     static std::vector<ClockCal> cache(64);
     if (device < 0 || device >= 64) return set_error(BC_E_DEVICE, "device id out of range");
-    // stream-ordered scratch: a plain free would wait for the whole device
     uint64_t *d = nullptr;
-    BC_HIP(hipMallocAsync((void **)&d, 8, st));
+    BC_HIP(mem.get(&d, 1));
     uint64_t tick = 0, rtt = 0;
     double mid = 0;
-    if (!clock_sample(d, st, tick, mid, rtt)) {
-        (void)hipFreeAsync(d, st);
-        return set_error(BC_E_DEVICE, "clock calibration failed");
-    }
+    if (!clock_sample(d, st, tick, mid, rtt)) return set_error(BC_E_DEVICE, "clock calibration failed");
     std::lock_guard<std::mutex> g(mu);
     ClockCal &c = cache[device];
     if (!c.ok) {
@@ -369,10 +518,7 @@ bc_status device_clock(int device, hipStream_t st, ClockCal &out)
         std::this_thread::sleep_for(std::chrono::milliseconds(20));
         uint64_t tick2 = 0, rtt2 = 0;
         double mid2 = 0;
-        if (!clock_sample(d, st, tick2, mid2, rtt2)) {
-            (void)hipFreeAsync(d, st);
-            return set_error(BC_E_DEVICE, "clock calibration failed");
-        }
+        if (!clock_sample(d, st, tick2, mid2, rtt2)) return set_error(BC_E_DEVICE, "clock calibration failed");
         const double rate = (double)(tick2 - tick) / (mid2 - mid);
         c.ticks_per_ns = (rate > 0.098 && rate < 0.102) || !(rate > 0) ? 0.1 : rate;
         c.offset = (double)tick2 - c.ticks_per_ns * mid2;
@@ -380,7 +526,6 @@ bc_status device_clock(int device, hipStream_t st, ClockCal &out)
     } else if (rtt < 2000000) {
         c.offset = (double)tick - c.ticks_per_ns * mid;
     }
-    (void)hipFreeAsync(d, st);
     out = c;
     return BC_OK;
 }
@@ -411,25 +556,6 @@ void binom_column(uint32_t nmax, uint32_t q, std::vector<u128> &col, uint32_t &n
         if (!ov[q] && (c[q] >> 28) == 0) n_u28 = n;
     }
 }
-
-struct DevAlloc {
-    std::vector<void *> ptrs;
-    hipStream_t st;
-    explicit DevAlloc(hipStream_t s) : st(s) {}
-    ~DevAlloc()
-    {
-        for (void *p : ptrs) (void)hipFreeAsync(p, st);
-    }
-    template <typename T>
-    hipError_t get(T **p, uint64_t count)
-    {
-        void *v = nullptr;
-        hipError_t e = hipMallocAsync(&v, std::max<uint64_t>(count, 1) * sizeof(T), st);
-        if (e == hipSuccess) ptrs.push_back(v);
-        *p = (T *)v;
-        return e;
-    }
-};
 
 hipError_t fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) { return bcdev::launch_fill_u32(p, n, v, st); }
 
@@ -472,10 +598,11 @@ int lds_per_block(int device)
 struct Timer {
     hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool ok = true;
-    Timer()
+    explicit Timer(bool on)
     {
+        ok = on;
         for (auto &x : e)
-            if (hipEventCreate(&x) != hipSuccess) ok = false;
+            if (ok && hipEventCreate(&x) != hipSuccess) ok = false;
     }
     ~Timer()
     {
@@ -537,25 +664,68 @@ std::vector<uint32_t> order_by_cost_desc(const std::vector<uint64_t> &cost)
     return a;
 }
 
-// short_first: order the tasks job by job, cheapest job (by the cost proxy)
-// first, instead of all tasks by cost -- for served batches, where one job
-// that cannot meet its deadline must not hold back the others.
+// Where one run_jobs call takes its stream and device scratch from.
+struct Exec {
+    bool short_first = false;   // served batches: order the tasks job by job, cheapest
+                                // job (by the cost proxy) first, so that one job that
+                                // cannot meet its deadline does not hold back the others
+    void *fixed = nullptr;      // non-NULL: all scratch from this device region
+    uint64_t fixed_cap = 0;     //   of this many bytes (no allocation, no timing events)
+    bool *fixed_short = nullptr;   // set when the region was too small
+};
+
+bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, std::vector<bc_u128> &out,
+                        std::vector<bc_status> &item_status, bc_stats *stats, const Exec &ex, bool &read_back,
+                        DevAlloc *&mem_out);
+
+// Runs the jobs; item_status[i] is BC_OK only for a count that was read back
+// from the device.  When the call fails before that, every item gets the
+// call's status.
 bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::vector<bc_u128> &out,
-                   std::vector<bc_status> &item_status, bc_stats *stats, bool short_first = false)
+                   std::vector<bc_status> &item_status, bc_stats *stats, const Exec &ex = Exec())
+{
+    bool read_back = false;
+    DevAlloc *mem = nullptr;
+    bc_status s = run_jobs_impl(specs, opts, out, item_status, stats, ex, read_back, mem);
+    if (mem && ex.fixed_short && mem->fixed_short) *ex.fixed_short = true;
+    delete mem;   // stream-ordered release of the call's scratch
+    if (!read_back) {
+        const bc_status e = s == BC_OK ? set_error(BC_E_DEVICE, "internal: counts were not read back") : s;
+        item_status.assign(specs.size(), e);
+        out.assign(specs.size(), bc_u128{0, 0});
+        return e;
+    }
+    return s;
+}
+
+bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, std::vector<bc_u128> &out,
+                        std::vector<bc_status> &item_status, bc_stats *stats, const Exec &ex, bool &read_back,
+                        DevAlloc *&mem_out)
 {
     const size_t ns = specs.size();
     out.assign(ns, bc_u128{0, 0});
     item_status.assign(ns, BC_OK);
-    if (ns == 0) return BC_OK;
-    hipStream_t st = pick_stream(opts);
-    if (!st) return set_error(BC_E_DEVICE, "could not create a HIP stream");
+    if (ns == 0) {
+        read_back = true;
+        return BC_OK;
+    }
+    const bool short_first = ex.short_first;
+    hipStream_t st = ex.fixed ? (hipStream_t)(opts ? opts->stream : nullptr) : pick_stream(opts);
+    if (!st && !ex.fixed) return set_error(BC_E_DEVICE, "could not create a HIP stream");
     const int device = specs[0].g->device;
     BC_HIP(hipSetDevice(device));
     const uint32_t lds_words = (opts && opts->lds_words) ? opts->lds_words : bcdev::max_lds_words_per_wave();
     const uint32_t waves_per_cu = (opts && opts->waves_per_cu) ? std::min(12u, opts->waves_per_cu) : 12u;
     const bool instrument = opts && opts->instrument;
+    const uint32_t roots_per_wave = BC_OPT(opts, roots_per_wave, 0u);
+    const uint32_t switch_depth = BC_OPT(opts, switch_depth, 0u);
+    const uint32_t split_rows = BC_OPT(opts, split_rows, 0u);
+    const bool two_pass = BC_OPT(opts, root_build, 0u) == BC_ROOT_BUILD_TWO_PASS;
     const int ncu = cu_count(device);
     auto t_host0 = std::chrono::steady_clock::now();
+    mem_out = ex.fixed ? new DevAlloc(st, ex.fixed, ex.fixed_cap)
+                       : new DevAlloc(st, BC_OPT(opts, alloc, (const bc_allocator *)nullptr));
+    DevAlloc &mem = *mem_out;
 
     // 1. Resolve anchors.  A spec with AUTO and p == q (>= 3) gets both sides
     //    as candidate jobs; the cheaper by the candidate-pass proxy is kept.
@@ -626,14 +796,13 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         const uint64_t dl = specs[hj.spec].deadline_ns;
         if (dl) {
             if (!clock.ok) {
-                if (bc_status e = device_clock(device, st, clock)) return e;
+                if (bc_status e = device_clock(device, st, mem, clock)) return e;
             }
             const double t = clock.offset + clock.ticks_per_ns * (double)dl;
             d.deadline = t < 1.0 ? 1ull : (uint64_t)t;
         }
         tab_off[j + 1] = tab_off[j] + cols[j].size();
     }
-    DevAlloc mem(st);
     bcdev::Job *d_jobs;
     u128 *d_tab;
     bcdev::Slot *d_slots;
@@ -655,7 +824,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     BC_HIP(bcdev::launch_fill_slots(d_slots, nj + 1, st));
     BC_HIP(fill_u32((uint32_t *)d_queue, 16, 0u, st));
 
-    Timer tm;
+    Timer tm(stats != nullptr && !ex.fixed);
     tm.mark(0, st);
 
     // 3. pA == 1: degree sums.
@@ -672,9 +841,28 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     // The fused per-root kernel (LDS counting, rows bump-allocated on the
     // device) needs 144 KiB of LDS per block and a pool sized up front; the
     // two-kernel path (count, plan, rows) is the fallback.
-    const bool fused = lds_per_block(device) >= 148 * 1024;
+    const bool fused = !two_pass && lds_per_block(device) >= 148 * 1024;
+    // Counter scratch of the candidate passes: per block, three u32 arrays over
+    // the widest anchor side of any job (all zero between roots).  Blocks of
+    // every candidate-pass launch are capped at rs_blocks.
     bcdev::RootScratch rs{};
     uint32_t rs_blocks = 0;
+    {
+        uint32_t nA_all = 0;
+        for (uint32_t j = 0; j < nj; ++j)
+            if (!jobs[j].trivial_zero && jobs[j].pA >= 2) nA_all = std::max(nA_all, hjobs[j].nA);
+        if (nA_all) {
+            uint64_t nb = (uint64_t)ncu * 2;
+            if (ex.fixed)   // at most a quarter of the fixed region
+                nb = std::max<uint64_t>(1, std::min<uint64_t>(nb, mem.room() / 4 / (12ull * nA_all)));
+            rs_blocks = (uint32_t)nb;
+            rs.stride = nA_all;
+            BC_HIP(mem.get(&rs.cnt, (uint64_t)rs_blocks * nA_all));
+            BC_HIP(mem.get(&rs.touched, (uint64_t)rs_blocks * nA_all));
+            BC_HIP(mem.get(&rs.cand, (uint64_t)rs_blocks * nA_all));
+            BC_HIP(fill_u32(rs.cnt, (uint64_t)rs_blocks * nA_all, 0u, st));
+        }
+    }
 
     // 4a. Specs with both anchors as candidates: estimate each side's
     //     planning cost from a rank-stratified sample of its roots
@@ -709,16 +897,6 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             }
         }
         if (!sjobs.empty()) {
-            // the counter scratch is sized for any later pass too
-            uint32_t nA_all = 1;
-            for (uint32_t j = 0; j < nj; ++j)
-                if (!jobs[j].trivial_zero && jobs[j].pA >= 2) nA_all = std::max(nA_all, hjobs[j].nA);
-            rs_blocks = (uint32_t)ncu * 2;
-            rs.stride = nA_all;
-            BC_HIP(mem.get(&rs.cnt, (uint64_t)rs_blocks * nA_all));
-            BC_HIP(mem.get(&rs.touched, (uint64_t)rs_blocks * nA_all));
-            BC_HIP(mem.get(&rs.cand, (uint64_t)rs_blocks * nA_all));
-            BC_HIP(fill_u32(rs.cnt, (uint64_t)rs_blocks * nA_all, 0u, st));
             const uint64_t s_roots = sprefix.back();
             bcdev::Job *d_sj;
             uint64_t *d_sp, *d_soff, *d_spool;
@@ -731,7 +909,8 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             BC_HIP(hipMemcpyAsync(d_sj, sjobs.data(), sjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
             BC_HIP(hipMemcpyAsync(d_sp, sprefix.data(), sprefix.size() * 8, hipMemcpyHostToDevice, st));
             const uint32_t s_blocks = (uint32_t)std::min<uint64_t>(
-                s_roots, std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
+                std::min<uint64_t>(s_roots, rs_blocks),
+                std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
             BC_HIP(bcdev::launch_root_build(d_sj, d_sp, (uint32_t)sjobs.size(), s_roots, rs, d_spool, 1, s_blocks,
                                             d_queue + 6, d_sk, d_soff, d_slots, st));
             std::vector<uint32_t> sk(s_roots);
@@ -775,7 +954,6 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     // 4b. Candidate pass over all roots of jobs with pA >= 2.
     std::vector<uint32_t> cj;   // jobs in the candidate pass
     std::vector<uint64_t> root_prefix(1, 0);
-    uint32_t nA_max = 1;
     for (uint32_t j = 0; j < nj; ++j)
         if (!jobs[j].trivial_zero && !jobs[j].dropped && jobs[j].pA >= 2) cj.push_back(j);
     if (short_first)   // served batches: the small graphs' candidate passes first
@@ -784,12 +962,12 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         });
     for (uint32_t j : cj) {
         root_prefix.push_back(root_prefix.back() + (jobs[j].root_hi - jobs[j].root_lo));
-        nA_max = std::max(nA_max, hjobs[j].nA);
     }
     const uint64_t total_roots = root_prefix.back();
     std::vector<uint32_t> h_k(total_roots);
     std::vector<uint64_t> h_off;
-    const uint32_t root_blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(total_roots, 1), (uint64_t)ncu * 2);
+    const uint32_t root_blocks =
+        (uint32_t)std::min<uint64_t>(std::max<uint64_t>(total_roots, 1), std::max<uint32_t>(rs_blocks, 1));
     std::vector<bcdev::Job> cjobs;
     bcdev::Job *d_cjobs = nullptr;
     uint64_t *d_pool_fused = nullptr;
@@ -803,13 +981,6 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         BC_HIP(mem.get(&d_cjobs, cjobs.size()));
         BC_HIP(mem.get(&d_rp, root_prefix.size()));
         BC_HIP(mem.get(&d_k, total_roots));
-        if (rs_blocks == 0) {   // else the sample pass sized it for every pass (left all zero)
-            rs.stride = nA_max;
-            BC_HIP(mem.get(&rs.cnt, (uint64_t)root_blocks * nA_max));
-            BC_HIP(mem.get(&rs.touched, (uint64_t)root_blocks * nA_max));
-            BC_HIP(mem.get(&rs.cand, (uint64_t)root_blocks * nA_max));
-            BC_HIP(fill_u32(rs.cnt, (uint64_t)root_blocks * nA_max, 0u, st));
-        }
         BC_HIP(hipMemcpyAsync(d_cjobs, cjobs.data(), cjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
         BC_HIP(hipMemcpyAsync(d_rp, root_prefix.data(), root_prefix.size() * 8, hipMemcpyHostToDevice, st));
         if (fused) {
@@ -818,13 +989,17 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
             uint64_t nnz_sum = 0;
             for (uint32_t j : cj) nnz_sum += specs[jobs[j].spec].g->nnz;
             pool_cap = std::max<uint64_t>(1ull << 22, 32 * nnz_sum + (4ull << 20));
+            // a fixed region gives the pool at most a third of what is left;
+            // roots that find no room are rebuilt into an exactly sized pool
+            if (ex.fixed) pool_cap = std::max<uint64_t>(1, std::min<uint64_t>(pool_cap, mem.room() / 3 / 8));
             uint64_t *d_off;
             BC_HIP(mem.get(&d_off, total_roots));
             BC_HIP(mem.get(&d_pool_fused, pool_cap));
             // one block of kRbThreads per CU (its LDS table takes most of the
             // CU's LDS); a reduced waves_per_cu takes the same share of CUs
             const uint32_t fused_blocks = (uint32_t)std::min<uint64_t>(
-                total_roots, std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
+                std::min<uint64_t>(total_roots, rs_blocks),
+                std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
             BC_HIP(bcdev::launch_root_build(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, d_pool_fused, pool_cap,
                                             fused_blocks, d_queue + 4, d_k, d_off, d_slots, st));
             h_off.resize(total_roots);
@@ -956,7 +1131,8 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         // Enumeration grid: waves_per_cu wavefronts per CU; each wave owns a
         // slab big enough for the deepest task of this plan.
         uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ncu * waves_per_cu / bcdev::kWavesPerBlock);
-        const uint64_t slab_budget = 64ull << 30;   // bytes of HBM for all slabs
+        uint64_t slab_budget = 64ull << 30;   // bytes of HBM for all slabs
+        if (ex.fixed) slab_budget = std::min(slab_budget, mem.room() > 512 ? mem.room() - 512 : 0);
         while (blocks > 1 && (uint64_t)blocks * bcdev::kWavesPerBlock * slab_need * 8 > slab_budget) blocks /= 2;
         uint64_t *d_slab;
         BC_HIP(mem.get(&d_slab, (uint64_t)blocks * bcdev::kWavesPerBlock * slab_need));
@@ -968,7 +1144,10 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
         // launches with many tasks per wave take them 8 at a time (fewer
         // queue atomics and root searches; consecutive tasks share their
         // root's rows), small ones 4 at a time (a more even spread)
-        prm.task_chunk = tasks >= 1024ull * blocks * bcdev::kWavesPerBlock ? 8u : 4u;
+        prm.task_chunk = roots_per_wave ? roots_per_wave
+                                        : (tasks >= 1024ull * blocks * bcdev::kWavesPerBlock ? 8u : 4u);
+        prm.triple = switch_depth == 2 ? 0u : 1u;
+        prm.split_rows = split_rows;
         prm.pool = d_pool;
         prm.slab = d_slab;
         prm.slab_words = slab_need;
@@ -984,6 +1163,7 @@ bc_status run_jobs(const std::vector<JobSpec> &specs, const bc_opts *opts, std::
     std::vector<bcdev::Slot> hs(nj);
     BC_HIP(hipMemcpyAsync(hs.data(), d_slots, nj * sizeof(bcdev::Slot), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
+    read_back = true;
 
     // 6. Results.  Candidate jobs for the same spec: only the live one counts.
     bc_status overall = BC_OK;
@@ -1101,22 +1281,28 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
     std::vector<JobSpec> sp;
     std::vector<size_t> idx;
     const uint64_t dl = opts_deadline(opts);
+    int device = -1;
     for (size_t i = 0; i < n; ++i) {
+        if (!graphs[i]) continue;
+        if (device < 0) device = graphs[i]->device;
+        if (graphs[i]->device != device)
+            return set_error(BC_E_INVALID_ARG, "bc_count_batch: graphs on different devices");
+    }
+    for (size_t i = 0; i < n; ++i) {
+        out[i] = bc_u128{0, 0};
         if (!graphs[i] || p[i] < 1 || q[i] < 1 || p[i] > 32 || q[i] > 32) {
             item_status[i] = BC_E_INVALID_ARG;
             continue;
         }
-        if (graphs[i]->device != graphs[0]->device)
-            return set_error(BC_E_INVALID_ARG, "bc_count_batch: graphs on different devices");
-        item_status[i] = BC_OK;
+        item_status[i] = BC_E_PENDING;   // replaced below in every case
         idx.push_back(i);
         sp.push_back(JobSpec{graphs[i], p[i], q[i], opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false, dl});
     }
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
     if (sp.empty()) return BC_OK;
+    // ist holds the call's status for every item unless the counts were read back
     bc_status s = run_jobs(sp, opts, res, ist, st);
-    if (s != BC_OK && s != BC_E_DEVICE) return s;
     for (size_t t = 0; t < idx.size(); ++t) {
         item_status[idx[t]] = ist[t];
         out[idx[t]] = ist[t] == BC_OK ? res[t] : bc_u128{0, 0};
@@ -1193,10 +1379,13 @@ bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 
     }
     std::vector<bc_u128> res;
     std::vector<bc_status> ist;
-    bc_status s = run_jobs(sp, opts, res, ist, nullptr, true);
+    Exec ex;
+    ex.short_first = true;
+    // ist holds the call's status for every item unless the counts were read back
+    bc_status s = run_jobs(sp, opts, res, ist, nullptr, ex);
     for (size_t t = 0; t < idx.size(); ++t) {
-        status[idx[t]] = (s == BC_OK || s == BC_E_DEVICE) && t < ist.size() ? ist[t] : s;
-        out[idx[t]] = (status[idx[t]] == BC_OK && t < res.size()) ? res[t] : bc_u128{0, 0};
+        status[idx[t]] = ist[t];
+        out[idx[t]] = status[idx[t]] == BC_OK ? res[t] : bc_u128{0, 0};
     }
     return s;
 }

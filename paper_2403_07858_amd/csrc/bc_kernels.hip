@@ -1593,7 +1593,7 @@ __device__ __forceinline__ uint64_t cycles() { return __builtin_amdgcn_s_memtime
 // One (root, second vertex) task: the node {u, c_i} of the search tree.
 __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, const uint64_t *pool,
                          Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument,
-                         bool *cap_fail, bool *timed_out)
+                         bool triple, bool *cap_fail, bool *timed_out)
 {
     const uint32_t ln = lane_id();
     const uint32_t u = rt.root;
@@ -1882,7 +1882,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         uint32_t a = (uint32_t)stack[4 * d + 2];
         // a small node two levels above the leaves: its last three levels in
         // one matrix-core sweep, then the node is done
-        if (d + 3 == pA && a == 0 && m >= 3 && m <= kTripleRows && W2 <= kTileWords && s2n <= jb.n_u28 &&
+        if (triple && d + 3 == pA && a == 0 && m >= 3 && m <= kTripleRows && W2 <= kTileWords && s2n <= jb.n_u28 &&
             table_ready(tb, jb, jidx, s2n + 1)) {
             const uint32_t pcap = m * (m - 1) / 2;
             const uint64_t mark = (uint64_t)ar.lds_used | (ar.slab_used << 32);
@@ -2037,7 +2037,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             bool cap_fail = false, timed_out = past_deadline(jb.deadline);
             if (!timed_out)
                 run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct,
-                         instrument, &cap_fail, &timed_out);
+                         instrument, prm.triple != 0, &cap_fail, &timed_out);
             if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
             if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
         }

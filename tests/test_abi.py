@@ -106,3 +106,38 @@ def test_tune_batch_argument_errors(bc):
     base = bc.make_opts(waves_per_cu=8, lds_words=256)
     assert lib.bc_tune_batch(None, None, None, 0, ctypes.byref(base), ctypes.byref(tuned)) == bc.BC_OK
     assert tuned.waves_per_cu == 8 and tuned.lds_words == 256
+
+
+def test_option_values_checked_before_device_work(bc):
+    # a valid 1x1 graph with out-of-range option values: refused by bc_build
+    # before any device call (so this runs without a GPU)
+    args = (1, 1, _u([0, 1]), _i([0]), _u([0, 1]), _i([0]))
+    for bad in ({"order_key": 5}, {"switch_depth": 1}, {"switch_depth": 4}, {"roots_per_wave": 65},
+                {"root_build": 2}, {"anchor": 3}):
+        with pytest.raises(bc.BCError) as e:
+            bc.bc_build(*args, **bad)
+        assert e.value.status == bc.BC_E_INVALID_ARG, bad
+    half = bc.Allocator(lambda n, st: 0, lambda p, st: None)
+    half.struct.free = ctypes.cast(None, type(half.struct.free))
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_build(*args, allocator=half)
+    assert e.value.status == bc.BC_E_INVALID_ARG
+
+
+def test_older_shorter_opts_are_accepted(bc):
+    # struct_size covering only the first fields: later fields are not read
+    # (a garbage value past struct_size must not be seen as a bad option)
+    o = bc.make_opts(switch_depth=9)
+    o.struct_size = bc.bc_opts.timeout_ms.offset + 4
+    lib = bc._lib
+    args = (1, 1, _u([0, 1]), _i([0]), _u([0, 1]), _i([0]))
+    keep = []
+    cu = bc._csr(args[0], args[1], args[2], args[3], keep)
+    cv = bc._csr(args[1], args[0], args[4], args[5], keep)
+    # validation passes the option check and goes on; without a GPU the call
+    # may then fail on the device, but never with BC_E_INVALID_ARG
+    h = ctypes.c_void_p()
+    s = lib.bc_build(ctypes.byref(cu), ctypes.byref(cv), ctypes.byref(o), ctypes.byref(h))
+    assert s != bc.BC_E_INVALID_ARG
+    if s == bc.BC_OK:
+        lib.bc_free(h)

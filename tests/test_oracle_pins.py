@@ -281,3 +281,41 @@ def test_invalid_csr_rejected(oracle_lib):
     # id out of range
     with pytest.raises(oracle_lib.OracleError):
         oracle_lib.count_csr(1, 2, np.array([0, 1], dtype=np.uint64), np.array([5], dtype=np.uint32), 1, 1)
+
+
+def _per_root_brute(adj, n_u, p, q, key):
+    """Definition 1 split by root: every p-subset L adds C(|common N(L)|, q) to
+    the member of L that comes first in the order of `key` (vertex -> sort
+    key), i.e. the root that enumerates L."""
+    first = {u: 0 for u in range(n_u)}
+    for L in itertools.combinations(range(n_u), p):
+        common = set.intersection(*(adj[x] for x in L))
+        first[min(L, key=key)] += math.comb(len(common), q)
+    return first
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_per_root_values_by_brute_force(oracle_lib, seed):
+    # count_ranks entry r is the count of the root ranked r (pins the
+    # rank <-> vertex mapping, not only the sum)
+    g = _random_graph(11, 9, 0.5, 40 + seed)
+    adj_u = brute.adjacency_sets(g.n_u, g.indptr_u, g.indices_u)
+    adj_v = brute.adjacency_sets(g.n_v, g.indptr_v, g.indices_v)
+    for anchor, adj, n in (("U", adj_u, g.n_u), ("V", adj_v, g.n_v)):
+        deg = [len(a) for a in adj]
+        by_degree = sorted(range(n), key=lambda x: (deg[x], x))
+        for p, q in [(2, 2), (3, 2), (2, 3), (3, 3)]:
+            pa, qa = (p, q) if anchor == "U" else (q, p)
+            want = _per_root_brute(adj, n, pa, qa, key=lambda x: (deg[x], x))
+            got = oracle_lib.count_ranks(g, p, q, list(range(n)), anchor=anchor, order_key=oracle_lib.ORDER_DEGREE)
+            assert got == [want[by_degree[r]] for r in range(n)], (anchor, p, q)
+            assert len(set(got)) > 1   # the values differ, so a permutation would show
+        # the two-hop order with threshold q (Definition 2's key, ties by id)
+        qa = 2
+        size = [sum(1 for w in range(n) if w != x and len(adj[x] & adj[w]) >= qa) for x in range(n)]
+        by_two_hop = sorted(range(n), key=lambda x: (size[x], x))
+        pa = 3
+        p, q = (pa, qa) if anchor == "U" else (qa, pa)
+        want = _per_root_brute(adj, n, pa, qa, key=lambda x: (size[x], x))
+        got = oracle_lib.count_ranks(g, p, q, list(range(n)), anchor=anchor, order_key=oracle_lib.ORDER_TWO_HOP)
+        assert got == [want[by_two_hop[r]] for r in range(n)], (anchor, "two-hop")
