@@ -25,6 +25,17 @@ MFMA_I8_PEAK = 5.0e15
 # The leaf pair sums are the int8 product R R^T of 0/1 rows: one 64-bit word
 # of both rows is 64 multiply-adds, 128 operations.
 OPS_PER_WORD_PAIR = 2 * 64
+# One word-intersection (the unit of the enumeration): an 8-byte row word read
+# and ANDed with the parent's word, then counted: 2 v_and_b32 + 2
+# v_bcnt_u32_b32 on 32-bit lanes.
+BYTES_PER_WORD = 8
+INT_OPS_PER_WORD = 4
+# Nominal figures of MI355X (256 CUs at 2.4 GHz): LDS 128 B/clk/CU, integer
+# VALU 64 lanes/clk/CU, HBM3E 8 TB/s.  The LDS and VALU denominators of the
+# roofline are measured live by the microbenchmarks of libbc_peaks.so.
+LDS_NOMINAL = 256 * 2.4e9 * 128
+VALU_INT_NOMINAL = 256 * 2.4e9 * 64
+HBM_PEAK = 8.0e12
 
 # HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
@@ -34,7 +45,7 @@ TRAFFIC_WORKLOAD = "power_law_2m"
 TRAFFIC_BYTES_Q44 = (1156403.0625 * 2.0 + 6162921.90625 * 1.0) * 1024
 
 WORKLOADS = {
-    "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4)]),
+    "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4), (5, 5)]),
     # 1M x 400k, 20M edges: (6,6) does not finish on it (see the design notes);
     # these are the queries that do
     "power_law_20m": ("power_law_20m", [(3, 3), (4, 4), (5, 5)]),
@@ -59,13 +70,25 @@ def main():
     ap.add_argument("--workload", default="power_law_2m", choices=sorted(WORKLOADS))
     ap.add_argument("--queries", default=None, help="e.g. '4,4;4,6'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-roots", type=int, default=96)
+    ap.add_argument("--cpu-rank-lo", type=int, default=62000,
+                    help="first U degree rank of the roots the oracle and the device both count at (4,4)")
+    ap.add_argument("--cpu-rank-hi", type=int, default=63000)
+    ap.add_argument("--sweep", default="6:150,7:20,8:20",
+                    help="p=q queries counted once after the timed steps, each under a device time limit "
+                         "in seconds ('k:seconds,...'; empty = none)")
     ap.add_argument("--batch", action="store_true",
                     help="batched workload: 4096 Chung-Lu graphs with mixed (p,q), one batched launch "
                          "set against one launch set per graph")
     ap.add_argument("--serve", action="store_true",
                     help="served workload: 64 resident graphs, Poisson query streams")
     ap.add_argument("--batch-n", type=int, default=4096)
+    ap.add_argument("--c3", action="store_true",
+                    help="20M-edge workload: (6,6) over cost-balanced root ranges, and a bitmap-width sweep")
+    ap.add_argument("--ranges", type=int, default=16)
+    ap.add_argument("--range-cap-s", type=float, default=15.0)
+    ap.add_argument("--bitmap-sweep", default="64,128,256,512,1024,0")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave the batched-vs-per-query measurement out of the default line")
     ap.add_argument("--timeout-ms", type=int, default=0, help="device time limit per count (0 = none)")
     ap.add_argument("--serve-queries", type=int, default=200, help="queries per arrival rate")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000")
@@ -87,6 +110,8 @@ def main():
         return run_batch(args)
     if args.serve:
         return run_serve(args)
+    if args.c3:
+        return run_c3(args)
     gen_name, default_q = WORKLOADS[args.workload]
     queries = parse_queries(args.queries) if args.queries else default_q
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
@@ -99,6 +124,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read, {args.copy_calibration_mib} MiB written")
         del src, dst
+    peaks = measure_peaks(log)
     t0 = time.time()
     g = getattr(gg, gen_name)()
     log(f"[bench] generated {args.workload}: {g.manifest['edges']} edges in {time.time() - t0:.1f}s")
@@ -150,31 +176,41 @@ def main():
     roots = sum(st["roots"] for (_, _, _, st) in results[0])
     value = total_count / (ms_per_step / 1000)
 
-    # roofline of the enumeration kernel: algorithmic int8 matrix-core ops of
-    # its leaf pair sums per launch over its mean launch time (HIP events on
-    # its stream)
+    # roofline of the enumeration kernel (the dominant one): algorithmic
+    # word-intersections (leaf pairs and child filters, from the instrumented
+    # pass) x 8 bytes per launch, over its mean launch time (HIP events on the
+    # stream it runs on), against the LDS bandwidth measured on this device
     enum_ms = {}
     for r in results:
         for (p, q, c, st) in r:
             enum_ms.setdefault((p, q), []).append(st["ms_enumerate"])
-    ops = sum(OPS_PER_WORD_PAIR * algo[k][1]["pair_ops"] for k in algo)
+    words = sum(algo[k][1]["pair_ops"] + algo[k][1]["filter_ops"] for k in algo)
     launch_ms = sum(sum(v) / len(v) for v in enum_ms.values())
-    achieved = ops / (launch_ms / 1000) if launch_ms > 0 else 0.0
+    n_launch = len(enum_ms)
+    sec = launch_ms / 1000
+    achieved = BYTES_PER_WORD * words / sec if sec > 0 else 0.0
+    int_ops = INT_OPS_PER_WORD * words / sec if sec > 0 else 0.0
+    mfma_ops = sum(OPS_PER_WORD_PAIR * algo[k][1]["pair_ops"] for k in algo) / sec if sec > 0 else 0.0
+    traffic = traffic_bytes(args.workload, queries)
     per_query = []
     for (p, q) in queries:
         c, st = algo[(p, q)]
         ms = sum(enum_ms[(p, q)]) / len(enum_ms[(p, q)])
         tot = [st2 for r in results for (pp, qq, _, st2) in r if (pp, qq) == (p, q)]
         mt = sum(s["ms_total"] for s in tot) / len(tot)
+        w = st["pair_ops"] + st["filter_ops"]
         per_query.append({"p": p, "q": q, "count": str(c), "ms_total": round(mt, 3), "ms_enumerate": round(ms, 3),
-                          "bicliques_per_s": c / (mt / 1000), "anchor": "UV"[st["anchor"]],
-                          "tasks": st["tasks"],
-                          "pair_sum_ops_per_s": OPS_PER_WORD_PAIR * st["pair_ops"] / (ms / 1000) if ms > 0 else 0.0,
+                          "bicliques_per_s": c / (mt / 1000), "root_vertices_per_s": st["roots"] / (mt / 1000),
+                          "anchor": "UV"[st["anchor"]], "tasks": st["tasks"],
+                          "word_intersections": w,
+                          "lds_frac": (BYTES_PER_WORD * w / (ms / 1000)) / peaks["lds_bytes_per_s"] if ms > 0 else 0.0,
                           "leaf_pairs_per_s": st["pairs"] / (ms / 1000) if ms > 0 else 0.0})
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, queries[0], args.cpu_sample_roots, log)
+        cpu = cpu_baseline(g, G, stream, args.cpu_rank_lo, args.cpu_rank_hi, log)
+    sweep = capped_sweep(G, stream, args.sweep, log) if args.sweep else []
+    batch = batch_measure(args.batch_n, 1, args.timeout_ms, log) if args.batch_n and not args.no_batch else None
 
     line = {
         "metric": "bicliques counted/sec",
@@ -194,14 +230,51 @@ def main():
                    "sha256": g.manifest["sha256"]},
         "root_vertices_per_s": roots / (ms_per_step / 1000),
         "per_query": per_query,
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_I8_PEAK / 1e12,
-                     "unit": "TOP/s", "dtype": "int8", "frac": achieved / MFMA_I8_PEAK,
-                     "traffic": traffic_bytes(args.workload, queries),
-                     "traffic_unit": f"bytes per k_enumerate launch of (4,4) on {TRAFFIC_WORKLOAD}",
-                     "kernel": "k_enumerate"},
+        "roofline": {"bound": "lds", "kernel": "k_enumerate", "achieved": achieved / 1e9,
+                     "peak": peaks["lds_bytes_per_s"] / 1e9, "unit": "GB/s",
+                     "frac": achieved / peaks["lds_bytes_per_s"], "traffic": traffic,
+                     "traffic_unit": f"HBM bytes per k_enumerate launch of (4,4) on {TRAFFIC_WORKLOAD}",
+                     "algorithmic_bytes_per_launch": BYTES_PER_WORD * words / n_launch,
+                     "launch_ms_mean": launch_ms / n_launch, "launches_per_step": n_launch,
+                     "unit_of_work": "word-intersection: 8 B row word AND parent word + popcount",
+                     "peak_source": "measured: bc_peak_lds (libbc_peaks.so) on this device",
+                     "peak_nominal": LDS_NOMINAL / 1e9, "frac_of_nominal": achieved / LDS_NOMINAL,
+                     "valu_int": {"achieved_tops": int_ops / 1e12, "peak_tops": peaks["valu_int_ops_per_s"] / 1e12,
+                                  "frac": int_ops / peaks["valu_int_ops_per_s"],
+                                  "peak_nominal_tops": VALU_INT_NOMINAL / 1e12},
+                     "hbm": {"achieved_gb_s": (traffic / ((sum(enum_ms[(4, 4)]) / len(enum_ms[(4, 4)])) / 1000) / 1e9)
+                             if traffic and (4, 4) in enum_ms else None,
+                             "peak_gb_s": HBM_PEAK / 1e9},
+                     "mfma_equivalent": {"achieved_tops": mfma_ops / 1e12, "peak_tops": MFMA_I8_PEAK / 1e12,
+                                         "frac": mfma_ops / MFMA_I8_PEAK, "dtype": "int8",
+                                         "note": "leaf pair sums as the int8 product of bit-expanded rows"}},
         "cpu_baseline": cpu,
+        "capped_sweep": sweep,
+        "batched_vs_per_query_speedup": batch["batched_vs_per_query_speedup"] if batch else None,
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
+
+
+def measure_peaks(log):
+    """LDS bandwidth and integer VALU rate of this device (libbc_peaks.so)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2403_07858_amd", "libbc_peaks.so"))
+    for f in (lib.bc_peak_lds, lib.bc_peak_valu_int):
+        f.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        f.restype = ctypes.c_int
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    out = {}
+    for name, f, iters in (("lds_bytes_per_s", lib.bc_peak_lds, 2048), ("valu_int_ops_per_s", lib.bc_peak_valu_int, 8192)):
+        best = 0.0
+        for _ in range(3):
+            rc = f(iters, ctypes.byref(rate), ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"{name} microbenchmark failed with hip error {rc}")
+            best = max(best, rate.value)
+        out[name] = best
+        log(f"[bench] peak {name} = {best:.4g} ({ms.value:.2f} ms launch)")
+    return out
 
 
 def traffic_bytes(workload, queries):
@@ -218,29 +291,60 @@ def traffic_bytes(workload, queries):
     return TRAFFIC_BYTES_Q44
 
 
-def cpu_baseline(g, pq, n_roots, log):
-    """The oracle on a uniform sample of roots of the first query (its own
-    degree order, anchor chosen like the device: U when p <= q), all host
-    cores.  Roots above a per-root intersection budget are skipped, so the
-    rate covers the completed roots only."""
+def cpu_baseline(g, G, stream, rank_lo, rank_hi, log, pq=(4, 4)):
+    """The oracle (all host cores) and the device (bc_count_roots) on the
+    identical work: the roots with degree rank in [rank_lo, rank_hi) on the
+    U side, query (4,4).  Both counts must be equal."""
     import oracle
-    from paper_2403_07858_amd import graphgen as gg
+    from paper_2403_07858_amd import bc
 
     p, q = pq
-    anchor = "U" if p <= q else "V"
-    n = g.n_u if anchor == "U" else g.n_v
-    ranks = sorted({int(x % n) for x in gg.draws_u64(12345, 1, 0, n_roots)})
     threads = oracle.default_threads()
-    budget = 20_000_000
     t0 = time.perf_counter()
-    vals = oracle.count_ranks(g, p, q, ranks, anchor=anchor, order_key=oracle.ORDER_DEGREE, threads=threads,
-                              max_nodes=budget)
+    want = oracle.count(g, p, q, order_key=oracle.ORDER_DEGREE, rank_lo=rank_lo, rank_hi=rank_hi, threads=threads)
     dt = time.perf_counter() - t0
-    done = [v for v in vals if v is not None]
-    log(f"[bench] cpu oracle: {len(done)}/{len(ranks)} sampled roots in {dt:.1f}s")
-    return {"value": sum(done) / dt if dt > 0 else 0.0, "unit": "bicliques/s", "cores": threads, "kind": "oracle",
-            "sample": f"({p},{q}) anchor {anchor}: {len(done)} of {len(ranks)} uniformly sampled roots completed "
-                      f"(roots needing > {budget} intersections skipped), {dt:.1f}s wall"}
+    got, st = bc.bc_count_roots(G, p, q, bc.BC_ANCHOR_U, rank_lo, rank_hi, with_stats=True, stream=stream)
+    ms = []
+    for _ in range(5):
+        c, st = bc.bc_count_roots(G, p, q, bc.BC_ANCHOR_U, rank_lo, rank_hi, with_stats=True, stream=stream)
+        assert c == got
+        ms.append(st["ms_total"])
+    gpu_s = sorted(ms)[len(ms) // 2] / 1000
+    log(f"[bench] cpu oracle: ({p},{q}) ranks [{rank_lo},{rank_hi}) count {want} in {dt:.1f}s; "
+        f"device {got} in {gpu_s * 1e3:.2f} ms")
+    if got != want:
+        raise RuntimeError(f"device and oracle differ on the CPU-baseline sample: {got} vs {want}")
+    return {"value": want / dt if dt > 0 else 0.0, "unit": "bicliques/s", "cores": threads, "kind": "oracle",
+            "sample": f"({p},{q}) anchor U, roots of degree rank [{rank_lo},{rank_hi}) "
+                      f"({rank_hi - rank_lo} roots), count {want}",
+            "seconds": dt, "device_seconds_same_sample": gpu_s,
+            "device_value_same_sample": want / gpu_s if gpu_s > 0 else 0.0,
+            "device_speedup_same_sample": dt / gpu_s if gpu_s > 0 else 0.0}
+
+
+def capped_sweep(G, stream, spec, log):
+    """p = q queries beyond the timed step, each counted once under a device
+    time limit; a query that hits its limit is reported as capped (no count,
+    nothing extrapolated)."""
+    from paper_2403_07858_amd import bc
+
+    out = []
+    for part in spec.split(","):
+        pq, cap = part.split(":")
+        k = int(pq)
+        cap_s = float(cap)
+        t0 = time.perf_counter()
+        try:
+            c, st = bc.bc_count(G, k, k, with_stats=True, stream=stream, timeout_ms=int(cap_s * 1000))
+            dt = time.perf_counter() - t0
+            out.append({"p": k, "q": k, "status": "done", "count": str(c), "seconds": dt,
+                        "bicliques_per_s": c / dt, "anchor": "UV"[st["anchor"]], "cap_s": cap_s})
+        except bc.BCError as e:
+            dt = time.perf_counter() - t0
+            out.append({"p": k, "q": k, "status": "capped" if e.status == bc.BC_E_TIMEOUT else bc.bc_status_string(e.status),
+                        "count": None, "seconds": dt, "cap_s": cap_s})
+        log(f"[bench] sweep ({k},{k}): {out[-1]['status']} after {dt:.1f}s")
+    return out
 
 
 def _log(*a):
@@ -270,99 +374,159 @@ def _workers():
         return 8
 
 
-def run_batch(args):
-    """Batched counting: every graph with its own (p,q) in one batched launch
-    set, against one bc_count per graph on the same stream."""
+def batch_measure(n, steps, timeout_ms, log):
+    """The batched workload: n Chung-Lu graphs, each with its own (p,q), counted
+    by one batched launch set (schedule from the autotuner) and by one
+    bc_count per graph on the same stream; counts compared item by item."""
     import torch
 
     from paper_2403_07858_amd import bc
 
     t0 = time.time()
-    items = _generate(_batch_item, args.batch_n, _workers())
-    _log(f"[batch] generated {len(items)} graphs, {sum(g.n_edges for g, _, _ in items)} edges "
-         f"in {time.time() - t0:.1f}s")
+    items = _generate(_batch_item, n, _workers())
+    log(f"[batch] generated {len(items)} graphs, {sum(g.n_edges for g, _, _ in items)} edges "
+        f"in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     t0 = time.time()
     graphs = [bc.build_graph(g, stream=stream) for g, _, _ in items]
     ps = [p for _, p, _ in items]
     qs = [q for _, _, q in items]
-    _log(f"[batch] built {len(graphs)} graphs in {time.time() - t0:.1f}s")
-    opt = {"stream": stream, "timeout_ms": args.timeout_ms}
-
+    log(f"[batch] built {len(graphs)} graphs in {time.time() - t0:.1f}s")
+    opt = {"stream": stream, "timeout_ms": timeout_ms}
     # the batched path's autotuner picks the schedule on a sample of the items
     t0 = time.perf_counter()
-    tuned = bc.bc_tune_batch(graphs, ps, qs, stream=stream, timeout_ms=args.timeout_ms)
+    tuned = bc.bc_tune_batch(graphs, ps, qs, stream=stream, timeout_ms=timeout_ms)
     t_tune = time.perf_counter() - t0
-    _log(f"[batch] autotuner chose {tuned} in {t_tune * 1e3:.0f} ms")
+    log(f"[batch] autotuner chose {tuned} in {t_tune * 1e3:.0f} ms")
     opt.update(tuned)
-    # warmup: the batched path once, instrumented
-    vals, st, agg = bc.bc_count_batch(graphs, ps, qs, with_stats=True, instrument=True, **opt)
-    cyc = {k: agg[k] for k in ("cyc_setup", "cyc_compact", "cyc_pair", "cyc_filter")}
-    tot = sum(cyc.values()) or 1
-    _log(f"[batch] instrumented pass: ms_cand={agg['ms_candidates']:.1f} ms_plan={agg['ms_plan']:.1f} "
-         f"ms_rows={agg['ms_rows']:.1f} ms_enum={agg['ms_enumerate']:.1f} ms_total={agg['ms_total']:.1f} "
-         f"roots={agg['roots']} tasks={agg['tasks']} pairs={agg['pairs']} "
-         f"words/pair={agg['pair_ops'] / max(1, agg['pairs']):.2f} "
-         f"lane_use={agg['pairs'] / max(1, agg['pair_slots']):.2f} task_cycles={tot:.4g} cycle share " +
-         " ".join(f"{k[4:]}={v / tot:.2f}" for k, v in cyc.items()))
     vals, st, agg = bc.bc_count_batch(graphs, ps, qs, with_stats=True, **opt)
-    _log(f"[batch] timed-mode pass: ms_cand={agg['ms_candidates']:.1f} ms_plan={agg['ms_plan']:.1f} "
-         f"ms_rows={agg['ms_rows']:.1f} ms_enum={agg['ms_enumerate']:.1f} ms_total={agg['ms_total']:.1f}")
+    log(f"[batch] warm pass: ms_cand={agg['ms_candidates']:.1f} ms_plan={agg['ms_plan']:.1f} "
+        f"ms_rows={agg['ms_rows']:.1f} ms_enum={agg['ms_enumerate']:.1f} ms_total={agg['ms_total']:.1f}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         vals, st = bc.bc_count_batch(graphs, ps, qs, **opt)
     torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
-    _log(f"[batch] batched: {t_batch * 1e3:.1f} ms per pass")
-
-    single_vals, single_st, single_ms = [], [], []
+    t_batch = (time.perf_counter() - t0) / steps
+    log(f"[batch] batched: {t_batch * 1e3:.1f} ms per pass")
+    # the default schedule, for the autotuner's gain
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vals_d, st_d = bc.bc_count_batch(graphs, ps, qs, stream=stream, timeout_ms=timeout_ms)
+    torch.cuda.synchronize()
+    t_default = time.perf_counter() - t0
+    single_vals, single_st = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for G, p, q in zip(graphs, ps, qs):
-        t1 = time.perf_counter()
         try:
             single_vals.append(bc.bc_count(G, p, q, **opt))
             single_st.append(bc.BC_OK)
         except bc.BCError as e:
             single_vals.append(None)
             single_st.append(e.status)
-        single_ms.append((time.perf_counter() - t1) * 1e3)
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
-    _log(f"[batch] one launch set per graph: {t_single * 1e3:.1f} ms")
+    log(f"[batch] one launch set per graph: {t_single * 1e3:.1f} ms; default schedule batched: "
+        f"{t_default * 1e3:.1f} ms")
     mismatch = sum(1 for a, b, s, s2 in zip(vals, single_vals, st, single_st)
                    if s == bc.BC_OK and s2 == bc.BC_OK and a != b)
-    ok = sum(1 for s in st if s == bc.BC_OK)
-    slow = sorted(range(len(single_ms)), key=lambda i: -single_ms[i])[:5]
-    _log("[batch] slowest single counts: " + ", ".join(
-        f"#{i} ({ps[i]},{qs[i]}) |U|={items[i][0].n_u} {single_ms[i]:.0f}ms" for i in slow))
+    mismatch += sum(1 for a, b, s, s2 in zip(vals, vals_d, st, st_d) if s == bc.BC_OK and s2 == bc.BC_OK and a != b)
     total = sum(v for v, s in zip(vals, st) if s == bc.BC_OK)
+    return {"graphs": len(graphs), "edges": sum(g.n_edges for g, _, _ in items), "pq": "U{2..6}^2",
+            "queries_per_s": len(graphs) / t_batch, "bicliques_per_s": total / t_batch,
+            "ms_batched": t_batch * 1e3, "ms_per_query_launches": t_single * 1e3,
+            "batched_vs_per_query_speedup": t_single / t_batch,
+            "ms_batched_default_schedule": t_default * 1e3, "autotuner_gain": t_default / t_batch,
+            "schedule": tuned, "autotune_ms": t_tune * 1e3,
+            "completed": sum(1 for s in st if s == bc.BC_OK),
+            "statuses": {bc.bc_status_string(s): st.count(s) for s in set(st)},
+            "mismatches": mismatch}
+
+
+def run_batch(args):
+    """Batched counting as a bench line of its own."""
+    r = batch_measure(args.batch_n, args.steps, args.timeout_ms, _log)
     line = {
         "metric": "batched count queries/sec",
-        "value": len(graphs) / t_batch,
+        "value": r["queries_per_s"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": 1,
-        "ms_per_step": t_batch * 1e3,
+        "ms_per_step": r["ms_batched"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u128",
         "data": "synthetic",
-        "config": {"workload": "batch_chung_lu", "graphs": len(graphs),
-                   "edges": sum(g.n_edges for g, _, _ in items), "pq": "U{2..6}^2",
+        "config": {"workload": "batch_chung_lu", "graphs": r["graphs"], "edges": r["edges"], "pq": r["pq"],
                    "timeout_ms": args.timeout_ms},
-        "bicliques_per_s": total / t_batch,
-        "batched_vs_per_query_speedup": t_single / t_batch,
-        "schedule": tuned,
-        "autotune_ms": t_tune * 1e3,
-        "per_query_ms_total": t_single * 1e3,
-        "completed": ok,
-        "statuses": {bc.bc_status_string(s): st.count(s) for s in set(st)},
-        "mismatches_vs_single": mismatch,
+        "batch": r,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_c3(args):
+    """The 20M-edge power-law graph: (6,6) over 16 cost-balanced root ranges
+    of one anchor, each under a device time limit (completed and capped
+    ranges reported, nothing extrapolated), then the bitmap width swept at
+    (4,4): roots with more neighbours than W bits take the HTB path."""
+    import numpy as np
+    import torch
+
+    from paper_2403_07858_amd import bc, graphgen as gg
+
+    log = _log
+    t0 = time.time()
+    g = gg.power_law_20m()
+    log(f"[c3] generated {g.n_edges} edges in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    G = bc.build_graph(g, stream=stream)
+    # anchor V for (6,6) (the sampled rule's choice at p = q >= 5 on this graph);
+    # ranges of equal sum over roots of d^2 (a per-root cost proxy), by rank
+    dv = np.sort(g.degrees_v().astype(np.float64))   # ranks follow ascending degree
+    cum = np.cumsum(dv * dv)
+    cuts = [0] + [int(np.searchsorted(cum, cum[-1] * i / args.ranges)) for i in range(1, args.ranges)] + [g.n_v]
+    ranges = []
+    for lo, hi in zip(cuts, cuts[1:]):
+        t1 = time.perf_counter()
+        try:
+            c, st = bc.bc_count_roots(G, 6, 6, bc.BC_ANCHOR_V, lo, hi, with_stats=True, stream=stream,
+                                      timeout_ms=int(args.range_cap_s * 1000))
+            ranges.append({"rank_lo": lo, "rank_hi": hi, "status": "done", "count": str(c),
+                           "seconds": time.perf_counter() - t1})
+        except bc.BCError as e:
+            ranges.append({"rank_lo": lo, "rank_hi": hi, "status": "capped" if e.status == bc.BC_E_TIMEOUT
+                           else bc.bc_status_string(e.status), "count": None, "seconds": time.perf_counter() - t1})
+        log(f"[c3] (6,6) V ranks [{lo},{hi}): {ranges[-1]['status']} {ranges[-1]['seconds']:.1f}s")
+    done = [r for r in ranges if r["status"] == "done"]
+    done_count = sum(int(r["count"]) for r in done)
+    done_s = sum(r["seconds"] for r in done)
+    sweep = []
+    base = None
+    for w in [int(x) for x in args.bitmap_sweep.split(",")]:
+        c, st = bc.bc_count(G, 4, 4, anchor=bc.BC_ANCHOR_U, bitmap_bits=w, with_stats=True, stream=stream)
+        ms = []
+        for _ in range(2):
+            c2, st2 = bc.bc_count(G, 4, 4, anchor=bc.BC_ANCHOR_U, bitmap_bits=w, with_stats=True, stream=stream)
+            assert c2 == c
+            ms.append(st2["ms_total"])
+        base = c if base is None else base
+        assert c == base, "the bitmap width changed a count"
+        sweep.append({"bitmap_bits": w, "count": str(c), "ms_total": min(ms), "ms_enumerate": st2["ms_enumerate"]})
+        log(f"[c3] (4,4) bitmap_bits {w}: {min(ms):.1f} ms")
+    line = {
+        "metric": "bicliques counted/sec", "value": done_count / done_s if done_s else 0.0, "unit": "bicliques/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": done_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u128", "data": "synthetic",
+        "config": {"workload": "power_law_20m", "query": "(6,6) on V root ranges; (4,4) bitmap sweep",
+                   "n_u": g.n_u, "n_v": g.n_v, "edges": g.n_edges, "sha256": g.manifest["sha256"],
+                   "range_cap_s": args.range_cap_s},
+        "ranges": ranges, "ranges_done": len(done), "ranges_capped": len(ranges) - len(done),
+        "bitmap_sweep_44": sweep,
     }
     print(json.dumps(line), flush=True)
 

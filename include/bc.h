@@ -87,14 +87,26 @@ typedef struct {
 /* Vertex order keys of bc_build (Definition 2: vertex priority). */
 enum {
     BC_ORDER_DEGREE = 0,    /* ascending degree, ties by id (default) */
-    BC_ORDER_TWO_HOP = 1    /* ascending |N_2^k(x)|: same-side vertices sharing >= k neighbours with x,
+    BC_ORDER_TWO_HOP = 1,   /* ascending |N_2^k(x)|: same-side vertices sharing >= k neighbours with x,
                                k = bc_opts.order_k (0 = 2); ties by original id */
+    BC_ORDER_BORDER = 2     /* Border (Algorithm 2, Section V-B): the degree order, then up to
+                               bc_opts.border_iters (0 = 4096) greedy swaps per side that each remove
+                               the most 1-blocks (32-id blocks of a row holding one neighbour) */
 };
 
 /* Root-build paths (bc_opts.root_build). */
 enum {
     BC_ROOT_BUILD_AUTO = 0,      /* one fused kernel per root (LDS hash table) when the device has the LDS */
     BC_ROOT_BUILD_TWO_PASS = 1   /* candidate counts, host plan, then rows: two kernels with HBM counters */
+};
+
+/* Set representations of the enumeration (bc_opts.sets). */
+enum {
+    BC_SETS_LOCAL_BITMAP = 0,   /* per-root bitmap rows over the root's own neighbourhood (default) */
+    BC_SETS_HTB = 1,            /* the graph's hierarchical truncated bitmaps (Section V-A): a set is
+                                   32-bit words, each with its index; intersections binary-search the
+                                   indices, then AND the words */
+    BC_SETS_SORTED = 2          /* sorted adjacency lists intersected by binary search (Section III-B) */
 };
 
 /* Options.  Pass NULL for all defaults.  No field changes any count.
@@ -123,6 +135,16 @@ typedef struct {
                                   subtask per row to a device queue that idle wavefronts drain;
                                   0 = auto (256), 0xffffffff = never split */
     uint32_t root_build;       /* BC_ROOT_BUILD_AUTO / _TWO_PASS */
+    uint32_t sets;             /* BC_SETS_LOCAL_BITMAP / _HTB / _SORTED (the last two send every root
+                                  through the global-set path) */
+    uint32_t bitmap_bits;      /* BC_SETS_LOCAL_BITMAP: the widest root bitmap, in bits (= neighbours
+                                  of the root); roots with more neighbours take the HTB path
+                                  instead; 0 = no limit */
+    uint32_t border_iters;     /* bc_build, BC_ORDER_BORDER: swap steps per side (0 = 4096) */
+    uint64_t scratch_cap_bytes;/* device scratch the call may take (0 = no cap): the enumeration grid
+                                  shrinks to fit, and a call that cannot fit fails with BC_E_OOM */
+    uint32_t pure_dfs;         /* global-set path: nonzero visits a node's candidates one at a time, the
+                                  wavefront's lanes sharing each intersection (no BFS over siblings) */
 } bc_opts;
 
 /* Timings (milliseconds, measured with HIP events on the stream) and work
@@ -143,6 +165,7 @@ typedef struct {
     uint64_t pair_slots;       /* instrumented: lane-slots spent on them (pairs / pair_slots = lane use) */
     uint64_t cyc_pack;         /* instrumented: the part of cyc_compact spent in tasks whose common
                                   neighbourhood had to be bit-packed (spread over more words than it needs) */
+    uint64_t scratch_bytes;    /* device scratch the call took (all of it held until the call ends) */
 } bc_stats;
 
 /*
@@ -167,6 +190,15 @@ void bc_free(bc_graph *g);
 
 /* Sizes of a built graph. */
 bc_status bc_graph_info(const bc_graph *g, uint64_t *n_u, uint64_t *n_v, uint64_t *n_edges);
+
+/*
+ * Size of the hierarchical truncated bitmap (Section V-A) of one side's rows
+ * (0 = U's rows over V ids, 1 = V's rows over U ids) under the graph's
+ * vertex order: *words = 32-bit words over all rows, *one_blocks = those
+ * holding a single neighbour (the 1-blocks that Border reduces).  Builds the
+ * HTB if no count has needed it yet (it is kept with the graph).
+ */
+bc_status bc_htb_stats(bc_graph *g, int32_t side, uint64_t *words, uint64_t *one_blocks);
 
 /*
  * rank_of[x] for every vertex x of one side (0 = U, 1 = V), in original ids:
@@ -218,14 +250,27 @@ bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const
                          size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st);
 
 /*
+ * bc_scratch_estimate -- an upper bound on the device scratch of bc_count(g,
+ * p, q) run with opts->waves_per_cu (0 = 12) and scratch_cap_bytes set to
+ * that bound (a capped call never takes more; the server admits queries by
+ * these estimates and caps each batch at their sum).  Per-root sizes are
+ * taken at their bounds over the graph (candidates, row words), for either
+ * anchor; the enumeration slabs are charged at most 8 GiB.
+ */
+bc_status bc_scratch_estimate(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts, uint64_t *bytes);
+
+/*
  * bc_tune_batch -- chooses a schedule for bc_count_batch over the same items
- * (the paper has no batching; this is the batched path's autotuner).  The
- * candidates are the persistent-grid occupancy (bc_opts.waves_per_cu 12, 8,
- * 4) and the per-wavefront LDS arena (bc_opts.lds_words 600, 256); each is
- * timed on an evenly spaced sample of the items (every 16th, at least 8) and
- * *tuned receives base (NULL = defaults) with the fastest pair.  No count
- * depends on these options.  A sample item that fails (e.g. over base's time
- * limit) counts as taking the whole limit.  Returns argument or device errors.
+ * (the paper has no batching; this is the batched path's autotuner).  It
+ * times bc_count_batch on an evenly spaced sample of the items (every 16th,
+ * at least 8) and tunes one option after another, each keeping the value
+ * with the shortest sample time (coordinate descent, after one warm-up run):
+ * waves_per_cu (12, 8, 4), lds_words (default, 256), roots_per_wave (auto,
+ * 2, 4, 16), switch_depth (3, 2) and, when a sampled item has min(p, q) >= 5,
+ * split_rows (default, 64, 256, 1024).  *tuned receives base (NULL =
+ * defaults) with the chosen values.  No count depends on these options.  A
+ * sample item that fails (e.g. over base's time limit) counts as taking the
+ * whole limit.  Returns argument or device errors.
  */
 bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
                         const bc_opts *base, bc_opts *tuned);

@@ -15,6 +15,15 @@ import os
 
 import numpy as np
 
+# torch first: its HIP runtime (torch/lib/libamdhip64.so, soname
+# libamdhip64.so.7) is then the one libbc.so binds to.  Loaded the other way
+# round, the process would hold two HIP runtimes, and torch's could not
+# open the GPU that the first one holds.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is part of this environment
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbc.so")
 
@@ -32,8 +41,9 @@ BC_E_PENDING = -10
 BC_E_NOT_FOUND = -11
 
 BC_ANCHOR_AUTO, BC_ANCHOR_U, BC_ANCHOR_V = -1, 0, 1
-BC_ORDER_DEGREE, BC_ORDER_TWO_HOP = 0, 1
+BC_ORDER_DEGREE, BC_ORDER_TWO_HOP, BC_ORDER_BORDER = 0, 1, 2
 BC_ROOT_BUILD_AUTO, BC_ROOT_BUILD_TWO_PASS = 0, 1
+BC_SETS_LOCAL_BITMAP, BC_SETS_HTB, BC_SETS_SORTED = 0, 1, 2
 
 
 class bc_u128(ctypes.Structure):
@@ -64,7 +74,9 @@ class bc_opts(ctypes.Structure):
                 ("alloc", ctypes.POINTER(bc_allocator)), ("order_key", ctypes.c_int32),
                 ("order_k", ctypes.c_uint32), ("roots_per_wave", ctypes.c_uint32),
                 ("switch_depth", ctypes.c_uint32), ("split_rows", ctypes.c_uint32),
-                ("root_build", ctypes.c_uint32)]
+                ("root_build", ctypes.c_uint32), ("sets", ctypes.c_uint32), ("bitmap_bits", ctypes.c_uint32),
+                ("border_iters", ctypes.c_uint32), ("scratch_cap_bytes", ctypes.c_uint64),
+                ("pure_dfs", ctypes.c_uint32)]
 
 
 class Allocator:
@@ -74,17 +86,20 @@ class Allocator:
     or graph uses it."""
 
     def __init__(self, alloc, free):
+        self.errors = []   # exceptions the callables raised (a raising alloc is a failed allocation)
+
         def _a(_ctx, n, st):
             try:
                 return alloc(int(n), int(st or 0)) or None
-            except Exception:   # a raising hook is an allocation failure
+            except Exception as e:
+                self.errors.append(repr(e))
                 return None
 
         def _f(_ctx, ptr, st):
             try:
                 free(int(ptr), int(st or 0))
-            except Exception:
-                pass
+            except Exception as e:
+                self.errors.append(repr(e))
 
         self._a, self._f = _ALLOC_FN(_a), _FREE_FN(_f)
         self.struct = bc_allocator(None, self._a, self._f)
@@ -95,6 +110,7 @@ def torch_allocator(device=None) -> Allocator:
     stream the library passes)."""
     import torch
 
+    torch.cuda.init()   # the caching allocator must exist before the library calls into it
     dev = torch.cuda.current_device() if device is None else device
     return Allocator(lambda n, st: torch.cuda.caching_allocator_alloc(n, dev, st),
                      lambda ptr, st: torch.cuda.caching_allocator_delete(ptr))
@@ -108,7 +124,7 @@ class bc_stats(ctypes.Structure):
                 ("pair_ops", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64),
                 ("cyc_setup", ctypes.c_uint64), ("cyc_compact", ctypes.c_uint64), ("cyc_pair", ctypes.c_uint64),
                 ("cyc_filter", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("pair_slots", ctypes.c_uint64),
-                ("cyc_pack", ctypes.c_uint64)]
+                ("cyc_pack", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -127,10 +143,12 @@ def _load():
         "bc_free": ([P], None),
         "bc_graph_info": ([P, P, P, P], I32),
         "bc_ranks": ([P, I32, P], I32),
+        "bc_htb_stats": ([P, I32, P, P], I32),
         "bc_count": ([P, U32, U32, P, P, P], I32),
         "bc_count_roots": ([P, U32, U32, I32, U64, U64, P, P, P], I32),
         "bc_count_batch": ([P, P, P, SZ, P, P, P, P], I32),
         "bc_tune_batch": ([P, P, P, SZ, P, P], I32),
+        "bc_scratch_estimate": ([P, U32, U32, P, P], I32),
         "bc_status_string": ([I32], ctypes.c_char_p),
         "bc_last_error": ([], ctypes.c_char_p),
     }
@@ -143,8 +161,8 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_count", "bc_count_roots", "bc_count_batch",
-            "bc_tune_batch", "bc_status_string", "bc_last_error")
+EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_htb_stats", "bc_count", "bc_count_roots", "bc_count_batch",
+            "bc_tune_batch", "bc_scratch_estimate", "bc_status_string", "bc_last_error")
 
 
 class BCError(RuntimeError):
@@ -175,7 +193,8 @@ def _stream_handle(stream):
 
 def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, instrument=False,
               timeout_ms=0, allocator=None, order_key=BC_ORDER_DEGREE, order_k=0, roots_per_wave=0,
-              switch_depth=0, split_rows=0, root_build=BC_ROOT_BUILD_AUTO) -> bc_opts:
+              switch_depth=0, split_rows=0, root_build=BC_ROOT_BUILD_AUTO, sets=0, bitmap_bits=0,
+              border_iters=0, scratch_cap_bytes=0, pure_dfs=False) -> bc_opts:
     o = bc_opts()
     o.struct_size = ctypes.sizeof(bc_opts)
     o.stream = _stream_handle(stream)
@@ -192,6 +211,11 @@ def make_opts(stream=None, anchor=BC_ANCHOR_AUTO, lds_words=0, waves_per_cu=0, i
     o.switch_depth = switch_depth
     o.split_rows = split_rows
     o.root_build = root_build
+    o.sets = sets
+    o.bitmap_bits = bitmap_bits
+    o.border_iters = border_iters
+    o.scratch_cap_bytes = scratch_cap_bytes
+    o.pure_dfs = 1 if pure_dfs else 0
     return o
 
 
@@ -275,6 +299,15 @@ def bc_count(g: Graph, p: int, q: int, with_stats=False, **opt):
     return (out.value, st.as_dict()) if with_stats else out.value
 
 
+def bc_htb_stats(g: Graph, side: int):
+    """(words, one_blocks) of the HTB of one side's rows."""
+    w, o = ctypes.c_uint64(), ctypes.c_uint64()
+    s = _lib.bc_htb_stats(g.handle, side, ctypes.byref(w), ctypes.byref(o))
+    if s != BC_OK:
+        raise BCError(s, "bc_htb_stats")
+    return w.value, o.value
+
+
 def bc_count_roots(g: Graph, p: int, q: int, anchor: int, rank_lo: int, rank_hi: int, with_stats=False, **opt):
     """Partial count over roots with rank in [rank_lo, rank_hi) on the anchor side."""
     o = make_opts(**opt)
@@ -305,9 +338,19 @@ def bc_count_batch(graphs, ps, qs, with_stats=False, **opt):
     return res + (agg.as_dict(),) if with_stats else res
 
 
+def bc_scratch_estimate(g: Graph, p: int, q: int, **opt) -> int:
+    """Upper bound on the device scratch (bytes) of bc_count(g, p, q) capped at it."""
+    o = make_opts(**opt)
+    b = ctypes.c_uint64()
+    s = _lib.bc_scratch_estimate(g.handle, p, q, ctypes.byref(o), ctypes.byref(b))
+    if s != BC_OK:
+        raise BCError(s, "bc_scratch_estimate")
+    return b.value
+
+
 def bc_tune_batch(graphs, ps, qs, **opt) -> dict:
-    """Schedule options chosen for bc_count_batch over these items:
-    {"waves_per_cu": ..., "lds_words": ...} (pass them on with **)."""
+    """Schedule options chosen for bc_count_batch over these items, as a dict
+    of the TUNED_KNOBS (pass them on with **)."""
     n = len(graphs)
     hs = (ctypes.c_void_p * max(1, n))(*[g.handle for g in graphs])
     pa = np.ascontiguousarray(ps, dtype=np.uint32)
@@ -317,7 +360,10 @@ def bc_tune_batch(graphs, ps, qs, **opt) -> dict:
     s = _lib.bc_tune_batch(hs, pa.ctypes.data, qa.ctypes.data, n, ctypes.byref(base), ctypes.byref(tuned))
     if s != BC_OK:
         raise BCError(s, "bc_tune_batch")
-    return {"waves_per_cu": tuned.waves_per_cu, "lds_words": tuned.lds_words}
+    return {k: getattr(tuned, k) for k in TUNED_KNOBS}
+
+
+TUNED_KNOBS = ("waves_per_cu", "lds_words", "roots_per_wave", "switch_depth", "split_rows")
 
 
 # ---------------------------------------------------------------------------

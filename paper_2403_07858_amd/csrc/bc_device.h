@@ -29,6 +29,44 @@ struct Job {
     uint64_t deadline;      // device real-time clock tick after which the job gives up (0 = none)
     uint32_t n_u58;         // largest n with C(n, qA) < 2^58 (64 such values add up in 64 bits)
     uint32_t n_u28;         // largest n with C(n, qA) < 2^28 (16 such values add up in 32 bits)
+    // hierarchical truncated bitmap of side A's rows (Section V-A): the row of
+    // x is the 32-bit words htb_idx/htb_val[htb_off[x] .. htb_off[x+1]), word
+    // i holding B ids 32i .. 32i+31 (bit j = id 32i + j); NULL when unused
+    const uint64_t *htb_off;
+    const uint32_t *htb_idx;
+    const uint32_t *htb_val;
+};
+
+// One root of the global-set path (set intersections over the graph's own
+// adjacency: HTB words or sorted id lists), in schedule order.
+struct SetRoot {
+    uint64_t id_off;        // its candidate ids: ids[id_off .. id_off + k)
+    uint64_t task_begin;    // global index of its first task
+    uint32_t job;
+    uint32_t root;
+    uint32_t k;
+    uint32_t n_tasks;       // k - (pA - 2)
+};
+
+enum : uint32_t { SETS_HTB = 1, SETS_SORTED = 2 };
+
+struct Slot;
+
+struct SetParams {
+    const Job *jobs;
+    const SetRoot *roots;
+    uint32_t n_roots;
+    uint32_t task_chunk;
+    uint64_t n_tasks;
+    const uint32_t *ids;    // candidate ids of every root
+    uint32_t mode;          // SETS_HTB or SETS_SORTED
+    uint32_t instrument;
+    uint32_t pure_dfs;      // nonzero: siblings one at a time, the lanes sharing each intersection
+    uint32_t pad;
+    uint64_t *slab;         // per-wave scratch
+    uint64_t slab_words;
+    unsigned long long *queue;
+    Slot *slots;
 };
 
 // One root that owns enumeration tasks, in schedule (cost) order.
@@ -88,8 +126,13 @@ struct EnumParams {
     uint32_t lds_words;     // per-wave LDS words actually used (<= compiled cap)
     uint32_t instrument;
     uint32_t triple;        // nonzero: small nodes three levels above the leaves take the triple sweep
-    uint32_t split_rows;    // level-2 blocks with more rows are split into queued subtasks (0 = default)
-    unsigned long long *queue;   // task counter
+    uint32_t split_rows;    // level-2 blocks with more rows are split into queued subtasks
+    uint32_t split_cap;     // subtask ring entries (0 = no splitting)
+    uint4 *ring;            // subtask ring, split_cap entries, all zero at launch
+    unsigned long long *sub_head;   // subtask entries claimed (zero at launch)
+    unsigned long long *sub_tail;   // subtask entries reserved (zero at launch)
+    unsigned long long *queue;   // task counter: tasks popped in the low 40 bits; with splitting on,
+                                 // wavefronts still running a popped chunk in the bits above
     Slot *slots;
 };
 
@@ -115,6 +158,12 @@ hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t 
                              uint64_t *pool, RootScratch scratch, uint32_t n_blocks,
                              unsigned long long *queue, Slot *slots, hipStream_t stream);
 hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream);
+// Candidate ids of the global-set roots: for root r, the w > u sharing >= qA
+// neighbours with u, in no particular order, written to ids[roots[r].id_off ..].
+hipError_t launch_cand_ids(const Job *jobs, const SetRoot *roots, uint32_t n_roots, uint32_t *ids,
+                           RootScratch scratch, uint32_t n_blocks, unsigned long long *queue, Slot *slots,
+                           hipStream_t stream);
+hipError_t launch_enumerate_sets(const SetParams &prm, uint32_t n_blocks, hipStream_t stream);
 
 uint32_t max_lds_words_per_wave();
 

@@ -13,6 +13,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "bc_device.h"
@@ -75,11 +76,20 @@ struct Side {
     uint32_t max_deg = 0;
     double deg_pairs = 0;            // sum over the side's vertices of C(d, 2): the wedges that
                                      // a candidate pass anchored on the other side scans
+    uint64_t max_wedges = 0;         // max over the side's vertices u of sum_{v in N(u)} d(v): a
+                                     // bound on the candidates of any root
     std::vector<uint32_t> rank_of;   // original id -> rank
     std::vector<uint64_t> h_ptr;     // relabelled CSR on the host (by rank)
     uint64_t *d_ptr = nullptr;
     uint32_t *d_adj = nullptr;
     uint32_t *d_rpos = nullptr;      // per edge (a, b): position of a within N(b)
+    // hierarchical truncated bitmap of the rows (Section V-A), built on the
+    // first count that needs it: row x is words [htb_off[x], htb_off[x+1])
+    bool htb_ready = false;
+    std::vector<uint64_t> h_htb_off;
+    uint64_t *d_htb_off = nullptr;
+    uint32_t *d_htb_idx = nullptr;
+    uint32_t *d_htb_val = nullptr;
 };
 
 }  // namespace
@@ -88,6 +98,7 @@ struct bc_graph {
     Side side[2];
     uint64_t nnz = 0;
     int device = 0;
+    std::mutex htb_mu;         // guards the lazy HTB build of both sides
     bool hooked = false;       // device arrays came from `hook` (freed through it)
     bc_allocator hook{};
 };
@@ -124,14 +135,17 @@ bc_status check_opts(const bc_opts *o)
     if (al && (!al->alloc || !al->free))
         return set_error(BC_E_INVALID_ARG, "bc_opts.alloc needs both alloc and free");
     const int32_t ok = BC_OPT(o, order_key, (int32_t)BC_ORDER_DEGREE);
-    if (ok != BC_ORDER_DEGREE && ok != BC_ORDER_TWO_HOP)
-        return set_error(BC_E_INVALID_ARG, "bc_opts.order_key must be BC_ORDER_DEGREE or BC_ORDER_TWO_HOP");
+    if (ok != BC_ORDER_DEGREE && ok != BC_ORDER_TWO_HOP && ok != BC_ORDER_BORDER)
+        return set_error(BC_E_INVALID_ARG, "bc_opts.order_key must be BC_ORDER_DEGREE, _TWO_HOP or _BORDER");
     if (BC_OPT(o, roots_per_wave, 0u) > 64) return set_error(BC_E_INVALID_ARG, "bc_opts.roots_per_wave must be 0..64");
     const uint32_t sd = BC_OPT(o, switch_depth, 0u);
     if (sd != 0 && sd != 2 && sd != 3) return set_error(BC_E_INVALID_ARG, "bc_opts.switch_depth must be 0, 2 or 3");
     const uint32_t rb = BC_OPT(o, root_build, 0u);
     if (rb != BC_ROOT_BUILD_AUTO && rb != BC_ROOT_BUILD_TWO_PASS)
         return set_error(BC_E_INVALID_ARG, "bc_opts.root_build must be BC_ROOT_BUILD_AUTO or _TWO_PASS");
+    const uint32_t sets = BC_OPT(o, sets, 0u);
+    if (sets != BC_SETS_LOCAL_BITMAP && sets != BC_SETS_HTB && sets != BC_SETS_SORTED)
+        return set_error(BC_E_INVALID_ARG, "bc_opts.sets must be BC_SETS_LOCAL_BITMAP, _HTB or _SORTED");
     return BC_OK;
 }
 
@@ -180,6 +194,137 @@ void key_order(uint64_t n, const std::vector<uint64_t> &key, std::vector<uint32_
     std::stable_sort(id_of_rank.begin(), id_of_rank.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
     rank_of.resize(n);
     for (uint64_t r = 0; r < n; ++r) rank_of[id_of_rank[r]] = (uint32_t)r;
+}
+
+// Border (Algorithm 2, Section V-B): reorders the vertices of one layer so
+// that the other layer's rows, cut into blocks of 32 consecutive positions
+// (the words of their HTB), have fewer blocks holding a single neighbour
+// (1-blocks).  Starts from `order` (positions, e.g. the degree order) and
+// repeats at most `iters` times: take the vertex v_m sitting in the most
+// 1-blocks; the candidates are the vertices sharing the fewest rows with
+// v_m; swap v_m with the candidate whose swap removes the most 1-blocks
+// (the profit x_m + x_n - y_m - y_n), if any does.  Rows are given over the
+// layer's vertex ids (rows_o with offsets ptr_o); cols_x lists, for each
+// vertex of the layer, the rows it is in.  Returns the new order (id at
+// each position).
+std::vector<uint32_t> border_order(uint64_t n, const std::vector<uint32_t> &order, uint64_t n_rows,
+                                   const uint64_t *ptr_o, const std::vector<uint32_t> &rows_o,
+                                   const uint64_t *ptr_x, const std::vector<uint32_t> &cols_x, uint64_t iters)
+{
+    constexpr uint32_t kCand = 64;   // candidates whose profit is evaluated per step (see the design notes)
+    std::vector<uint32_t> xat(order), pos(n);
+    for (uint64_t i = 0; i < n; ++i) pos[xat[i]] = (uint32_t)i;
+    // per row: occupied blocks and how many of its members each holds
+    std::vector<std::unordered_map<uint32_t, uint32_t>> cnt(n_rows);
+    for (uint64_t r = 0; r < n_rows; ++r)
+        for (uint64_t e = ptr_o[r]; e < ptr_o[r + 1]; ++e) cnt[r][pos[rows_o[e]] >> 5]++;
+    std::vector<int64_t> ones(n, 0);   // 1-blocks each vertex sits in
+    for (uint64_t x = 0; x < n; ++x)
+        for (uint64_t e = ptr_x[x]; e < ptr_x[x + 1]; ++e) ones[x] += cnt[cols_x[e]][pos[x] >> 5] == 1;
+    std::vector<char> stuck(n, 0);     // no profitable swap found for it
+    std::vector<uint32_t> overlap(n, 0);
+    std::vector<uint32_t> touched;
+    // the single member of block b of row r (the block must hold exactly one)
+    auto alone = [&](uint32_t r, uint32_t b) -> uint32_t {
+        for (uint64_t e = ptr_o[r]; e < ptr_o[r + 1]; ++e)
+            if ((pos[rows_o[e]] >> 5) == b) return rows_o[e];
+        return 0xffffffffu;
+    };
+    // 1-blocks removed by swapping the positions of a and b
+    auto profit = [&](uint32_t a, uint32_t b) -> int64_t {
+        const uint32_t ba = pos[a] >> 5, bb = pos[b] >> 5;
+        if (ba == bb) return 0;
+        int64_t delta = 0;   // change in the number of 1-blocks
+        auto moved = [&](uint32_t r, uint32_t from, uint32_t to) {
+            const auto &m = cnt[r];
+            const uint32_t cf = m.count(from) ? m.at(from) : 0, ct = m.count(to) ? m.at(to) : 0;
+            delta += (int64_t)(cf - 1 == 1) - (int64_t)(cf == 1);
+            delta += (int64_t)(ct + 1 == 1) - (int64_t)(ct == 1);
+        };
+        // rows of a without b: a leaves ba for bb; rows of b without a: the reverse
+        for (uint64_t e = ptr_x[a]; e < ptr_x[a + 1]; ++e) overlap[cols_x[e]] = 1;
+        for (uint64_t e = ptr_x[b]; e < ptr_x[b + 1]; ++e) {
+            const uint32_t r = cols_x[e];
+            if (overlap[r]) overlap[r] = 2;
+            else moved(r, bb, ba);
+        }
+        for (uint64_t e = ptr_x[a]; e < ptr_x[a + 1]; ++e) {
+            const uint32_t r = cols_x[e];
+            if (overlap[r] == 1) moved(r, ba, bb);
+            overlap[r] = 0;
+        }
+        return -delta;
+    };
+    (void)touched;
+    for (uint64_t it = 0; it < iters; ++it) {
+        // Step 1: the vertex in the most 1-blocks
+        uint32_t vm = 0xffffffffu;
+        for (uint64_t x = 0; x < n; ++x)
+            if (!stuck[x] && ones[x] > 0 && (vm == 0xffffffffu || ones[x] > ones[vm])) vm = (uint32_t)x;
+        if (vm == 0xffffffffu) break;
+        // Step 2: rows shared with v_m, for every vertex (wedge scan); the
+        // candidates have the fewest, best first by their own 1-blocks
+        std::vector<uint32_t> shared(n, 0);
+        for (uint64_t e = ptr_x[vm]; e < ptr_x[vm + 1]; ++e) {
+            const uint32_t r = cols_x[e];
+            for (uint64_t f = ptr_o[r]; f < ptr_o[r + 1]; ++f) shared[rows_o[f]]++;
+        }
+        uint32_t least = 0xffffffffu;
+        for (uint64_t x = 0; x < n; ++x)
+            if (x != vm) least = std::min(least, shared[x]);
+        std::vector<uint32_t> cand;
+        for (uint64_t x = 0; x < n; ++x)
+            if (x != vm && shared[x] == least && (pos[x] >> 5) != (pos[vm] >> 5)) cand.push_back((uint32_t)x);
+        if (cand.size() > kCand) {
+            std::partial_sort(cand.begin(), cand.begin() + kCand, cand.end(),
+                              [&](uint32_t a, uint32_t b) { return ones[a] != ones[b] ? ones[a] > ones[b] : a < b; });
+            cand.resize(kCand);
+        }
+        // Step 3: the candidate with the highest profit
+        int64_t best = 0;
+        uint32_t vn = 0xffffffffu;
+        for (uint32_t x : cand) {
+            const int64_t pr = profit(vm, x);
+            if (pr > best) {
+                best = pr;
+                vn = x;
+            }
+        }
+        if (vn == 0xffffffffu) {
+            stuck[vm] = 1;
+            continue;
+        }
+        // Step 4: swap, then update the block counts and the 1-block counts
+        // of every vertex whose block changed between one member and more
+        const uint32_t ba = pos[vm] >> 5, bb = pos[vn] >> 5;
+        std::vector<std::pair<uint32_t, uint32_t>> hit;   // (row, block) whose count changes
+        for (uint64_t e = ptr_x[vm]; e < ptr_x[vm + 1]; ++e) hit.push_back({cols_x[e], ba}), hit.push_back({cols_x[e], bb});
+        for (uint64_t e = ptr_x[vn]; e < ptr_x[vn + 1]; ++e) hit.push_back({cols_x[e], ba}), hit.push_back({cols_x[e], bb});
+        std::sort(hit.begin(), hit.end());
+        hit.erase(std::unique(hit.begin(), hit.end()), hit.end());
+        for (const auto &h : hit) {   // old singles lose their 1-block
+            auto f = cnt[h.first].find(h.second);
+            if (f != cnt[h.first].end() && f->second == 1) ones[alone(h.first, h.second)]--;
+        }
+        for (uint64_t e = ptr_x[vm]; e < ptr_x[vm + 1]; ++e) {
+            auto &m = cnt[cols_x[e]];
+            if (--m[ba] == 0) m.erase(ba);
+            m[bb]++;
+        }
+        for (uint64_t e = ptr_x[vn]; e < ptr_x[vn + 1]; ++e) {
+            auto &m = cnt[cols_x[e]];
+            if (--m[bb] == 0) m.erase(bb);
+            m[ba]++;
+        }
+        std::swap(xat[pos[vm]], xat[pos[vn]]);
+        std::swap(pos[vm], pos[vn]);
+        for (const auto &h : hit) {   // new singles gain one
+            auto f = cnt[h.first].find(h.second);
+            if (f != cnt[h.first].end() && f->second == 1) ones[alone(h.first, h.second)]++;
+        }
+        stuck[vn] = 0;
+    }
+    return xat;
 }
 
 // Degree of every vertex of side c.
@@ -273,9 +418,67 @@ void free_side(bc_graph *g, Side &s)
     graph_release(g, s.d_ptr);
     graph_release(g, s.d_adj);
     graph_release(g, s.d_rpos);
+    graph_release(g, s.d_htb_off);
+    graph_release(g, s.d_htb_idx);
+    graph_release(g, s.d_htb_val);
     s.d_ptr = nullptr;
     s.d_adj = nullptr;
     s.d_rpos = nullptr;
+    s.d_htb_off = nullptr;
+    s.d_htb_idx = nullptr;
+    s.d_htb_val = nullptr;
+}
+
+// The HTB of one side's rows (Section V-A): each neighbour id b goes to word
+// b / 32, bit b % 32; a row keeps its nonzero words in increasing word index
+// (Idx) with their values (Val), and Off gives each row's first word.  Built
+// once per graph side, on the host from the device rows, under htb_mu.
+bc_status ensure_htb(bc_graph *g, int side, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g->htb_mu);
+    Side &sd = g->side[side];
+    if (sd.htb_ready) return BC_OK;
+    std::vector<uint32_t> adj(g->nnz);
+    if (g->nnz) BC_HIP(hipMemcpyAsync(adj.data(), sd.d_adj, g->nnz * 4, hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    std::vector<uint64_t> off(sd.n + 1, 0);
+    std::vector<uint32_t> idx, val;
+    idx.reserve(g->nnz);
+    val.reserve(g->nnz);
+    for (uint64_t x = 0; x < sd.n; ++x) {
+        for (uint64_t e = sd.h_ptr[x]; e < sd.h_ptr[x + 1]; ++e) {
+            const uint32_t w = adj[e] >> 5, bit = 1u << (adj[e] & 31);
+            if (idx.size() > off[x] && idx.back() == w) val.back() |= bit;   // rows are sorted
+            else {
+                idx.push_back(w);
+                val.push_back(bit);
+            }
+        }
+        off[x + 1] = idx.size();
+    }
+    const uint64_t words = std::max<uint64_t>(1, idx.size());
+    hipError_t e = graph_alloc(g, (void **)&sd.d_htb_off, (sd.n + 1) * 8, st);
+    if (e == hipSuccess) e = graph_alloc(g, (void **)&sd.d_htb_idx, words * 4, st);
+    if (e == hipSuccess) e = graph_alloc(g, (void **)&sd.d_htb_val, words * 4, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sd.d_htb_off, off.data(), (sd.n + 1) * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !idx.empty())
+        e = hipMemcpyAsync(sd.d_htb_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !val.empty())
+        e = hipMemcpyAsync(sd.d_htb_val, val.data(), val.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        graph_release(g, sd.d_htb_off);
+        graph_release(g, sd.d_htb_idx);
+        graph_release(g, sd.d_htb_val);
+        sd.d_htb_off = nullptr;
+        sd.d_htb_idx = nullptr;
+        sd.d_htb_val = nullptr;
+        return hip_error(e, "HTB build");
+    }
+    sd.h_htb_off.swap(off);
+    sd.htb_ready = true;
+    return BC_OK;
 }
 
 }  // namespace
@@ -318,7 +521,18 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
         g->hook = *al;
     }
     std::vector<uint32_t> idU, idV;
-    if (BC_OPT(opts, order_key, (int32_t)BC_ORDER_DEGREE) == BC_ORDER_TWO_HOP) {
+    const int32_t okey = BC_OPT(opts, order_key, (int32_t)BC_ORDER_DEGREE);
+    if (okey == BC_ORDER_BORDER) {
+        // degree order first (Section V-B), then Border on each layer for the
+        // other layer's rows
+        key_order(U->n_rows, degree_key(U), idU, g->side[0].rank_of);
+        key_order(V->n_rows, degree_key(V), idV, g->side[1].rank_of);
+        const uint64_t it = BC_OPT(opts, border_iters, 0u) ? BC_OPT(opts, border_iters, 0u) : 4096u;
+        idU = border_order(U->n_rows, idU, V->n_rows, V->indptr, rowsV, U->indptr, rowsU, it);
+        idV = border_order(V->n_rows, idV, U->n_rows, U->indptr, rowsU, V->indptr, rowsV, it);
+        for (uint64_t r = 0; r < U->n_rows; ++r) g->side[0].rank_of[idU[r]] = (uint32_t)r;
+        for (uint64_t r = 0; r < V->n_rows; ++r) g->side[1].rank_of[idV[r]] = (uint32_t)r;
+    } else if (okey == BC_ORDER_TWO_HOP) {
         const uint32_t k = std::max(1u, BC_OPT(opts, order_k, 0u) ? BC_OPT(opts, order_k, 0u) : 2u);
         key_order(U->n_rows, two_hop_key(U, rowsU, V, rowsV, k), idU, g->side[0].rank_of);
         key_order(V->n_rows, two_hop_key(V, rowsV, U, rowsU, k), idV, g->side[1].rank_of);
@@ -339,6 +553,15 @@ extern "C" bc_status bc_build(const bc_csr *U, const bc_csr *V, const bc_opts *o
             const uint64_t d = sd.h_ptr[r + 1] - sd.h_ptr[r];
             sd.max_deg = std::max<uint32_t>(sd.max_deg, (uint32_t)d);
             sd.deg_pairs += 0.5 * (double)d * (double)(d ? d - 1 : 0);
+        }
+    }
+    for (int s = 0; s < 2; ++s) {
+        Side &sa = g->side[s];
+        const Side &sb = g->side[1 - s];
+        for (uint64_t r = 0; r < sa.n; ++r) {
+            uint64_t w = 0;
+            for (uint64_t e = sa.h_ptr[r]; e < sa.h_ptr[r + 1]; ++e) w += sb.h_ptr[adj[s][e] + 1] - sb.h_ptr[adj[s][e]];
+            sa.max_wedges = std::max(sa.max_wedges, w);
         }
     }
     // Reverse positions: for the edge (a, b) stored in a's row, the index of a
@@ -395,6 +618,27 @@ extern "C" bc_status bc_graph_info(const bc_graph *g, uint64_t *n_u, uint64_t *n
     return BC_OK;
 }
 
+extern "C" bc_status bc_htb_stats(bc_graph *g, int32_t side, uint64_t *words, uint64_t *one_blocks)
+{
+    g_last_error.clear();
+    if (!g || (side != 0 && side != 1) || !words || !one_blocks)
+        return set_error(BC_E_INVALID_ARG, "bc_htb_stats: bad argument");
+    hipStream_t st = own_stream();
+    if (!st) return set_error(BC_E_DEVICE, "could not create a HIP stream");
+    BC_HIP(hipSetDevice(g->device));
+    if (bc_status e = ensure_htb(g, side, st)) return e;
+    const Side &sd = g->side[side];
+    const uint64_t n_words = sd.h_htb_off.back();
+    std::vector<uint32_t> val(std::max<uint64_t>(1, n_words));
+    if (n_words) BC_HIP(hipMemcpyAsync(val.data(), sd.d_htb_val, n_words * 4, hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    uint64_t ones = 0;
+    for (uint64_t i = 0; i < n_words; ++i) ones += __builtin_popcount(val[i]) == 1;
+    *words = n_words;
+    *one_blocks = ones;
+    return BC_OK;
+}
+
 extern "C" bc_status bc_ranks(const bc_graph *g, int32_t side, uint32_t *rank_of)
 {
     if (!g || !rank_of || (side != 0 && side != 1)) return set_error(BC_E_INVALID_ARG, "bc_ranks: bad argument");
@@ -420,6 +664,8 @@ struct DevAlloc {
     uint8_t *fixed = nullptr;
     uint64_t fixed_cap = 0, fixed_used = 0;
     bool fixed_short = false;    // a request did not fit the fixed region
+    uint64_t cap = 0;            // nonzero: at most this many bytes in all (other sources)
+    uint64_t total = 0;          // bytes taken so far (nothing is released before the end)
     DevAlloc(hipStream_t s, const bc_allocator *h) : st(s), hook(h) {}
     DevAlloc(hipStream_t s, void *region, uint64_t cap) : st(s), fixed((uint8_t *)region), fixed_cap(cap) {}
     ~DevAlloc()
@@ -429,8 +675,12 @@ struct DevAlloc {
             else (void)hipFreeAsync(p, st);
         }
     }
-    // bytes left in the fixed region (unbounded for the other sources)
-    uint64_t room() const { return fixed ? fixed_cap - fixed_used : ~0ull; }
+    // bytes left in the fixed region or under the cap (else unbounded)
+    uint64_t room() const
+    {
+        if (fixed) return fixed_cap - fixed_used;
+        return cap ? (cap > total ? cap - total : 0) : ~0ull;
+    }
     hipError_t raw(void **p, uint64_t bytes)
     {
         bytes = (std::max<uint64_t>(bytes, 1) + 255) & ~255ull;
@@ -442,8 +692,10 @@ struct DevAlloc {
             }
             *p = fixed + fixed_used;
             fixed_used += bytes;
+            total += bytes;
             return hipSuccess;
         }
+        if (cap && bytes > room()) return hipErrorOutOfMemory;
         void *v = nullptr;
         if (hook) {
             v = hook->alloc(hook->ctx, bytes, st);
@@ -453,6 +705,7 @@ struct DevAlloc {
             if (e != hipSuccess) return e;
         }
         ptrs.push_back(v);
+        total += bytes;
         *p = v;
         return hipSuccess;
     }
@@ -664,6 +917,22 @@ std::vector<uint32_t> order_by_cost_desc(const std::vector<uint64_t> &cost)
     return a;
 }
 
+// Cost model of served deadlines: per enumeration depth p_A, the fewest
+// nanoseconds per unit of the whole-depth planning proxy (sum over a job's
+// roots of k^(p_A - 1) W1) seen so far in a served batch holding that one
+// job.  The proxy ignores pruning, so the fewest seen is the optimistic end:
+// a job is refused only when even that rate puts it far past its deadline.
+struct RateBook {
+    std::mutex mu;
+    double ns_per_unit[33] = {0};   // 0 = nothing seen yet
+};
+RateBook &rate_book()
+{
+    static RateBook rb;
+    return rb;
+}
+constexpr double kRefuseMargin = 4.0;   // refuse when the estimate exceeds 4x the time left
+
 // Where one run_jobs call takes its stream and device scratch from.
 struct Exec {
     bool short_first = false;   // served batches: order the tasks job by job, cheapest
@@ -672,6 +941,8 @@ struct Exec {
     void *fixed = nullptr;      // non-NULL: all scratch from this device region
     uint64_t fixed_cap = 0;     //   of this many bytes (no allocation, no timing events)
     bool *fixed_short = nullptr;   // set when the region was too small
+    uint64_t scratch_cap = 0;   // nonzero: the call's device scratch stays within this many bytes (the
+                                // enumeration grid shrinks to fit; what still does not fit is BC_E_OOM)
 };
 
 bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, std::vector<bc_u128> &out,
@@ -721,11 +992,15 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
     const uint32_t switch_depth = BC_OPT(opts, switch_depth, 0u);
     const uint32_t split_rows = BC_OPT(opts, split_rows, 0u);
     const bool two_pass = BC_OPT(opts, root_build, 0u) == BC_ROOT_BUILD_TWO_PASS;
+    const uint64_t scratch_cap = std::max<uint64_t>(ex.scratch_cap, BC_OPT(opts, scratch_cap_bytes, (uint64_t)0));
+    const uint32_t sets_opt = BC_OPT(opts, sets, (uint32_t)BC_SETS_LOCAL_BITMAP);
+    const uint32_t bitmap_bits = BC_OPT(opts, bitmap_bits, 0u);
     const int ncu = cu_count(device);
     auto t_host0 = std::chrono::steady_clock::now();
     mem_out = ex.fixed ? new DevAlloc(st, ex.fixed, ex.fixed_cap)
                        : new DevAlloc(st, BC_OPT(opts, alloc, (const bc_allocator *)nullptr));
     DevAlloc &mem = *mem_out;
+    mem.cap = ex.fixed ? 0 : scratch_cap;
 
     // 1. Resolve anchors.  A spec with AUTO and p == q (>= 3) gets both sides
     //    as candidate jobs; the cheaper by the candidate-pass proxy is kept.
@@ -810,7 +1085,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
     BC_HIP(mem.get(&d_jobs, nj));
     BC_HIP(mem.get(&d_tab, tab_off[nj]));
     BC_HIP(mem.get(&d_slots, nj + 1));   // slot nj: sample jobs
-    BC_HIP(mem.get(&d_queue, 8));
+    BC_HIP(mem.get(&d_queue, 12));
     {
         std::vector<u128> tab(tab_off[nj]);
         for (uint32_t j = 0; j < nj; ++j) {
@@ -822,7 +1097,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         BC_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
     }
     BC_HIP(bcdev::launch_fill_slots(d_slots, nj + 1, st));
-    BC_HIP(fill_u32((uint32_t *)d_queue, 16, 0u, st));
+    BC_HIP(fill_u32((uint32_t *)d_queue, 24, 0u, st));
 
     Timer tm(stats != nullptr && !ex.fixed);
     tm.mark(0, st);
@@ -853,7 +1128,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
             if (!jobs[j].trivial_zero && jobs[j].pA >= 2) nA_all = std::max(nA_all, hjobs[j].nA);
         if (nA_all) {
             uint64_t nb = (uint64_t)ncu * 2;
-            if (ex.fixed)   // at most a quarter of the fixed region
+            if (ex.fixed || mem.cap)   // at most a quarter of the fixed region or cap
                 nb = std::max<uint64_t>(1, std::min<uint64_t>(nb, mem.room() / 4 / (12ull * nA_all)));
             rs_blocks = (uint32_t)nb;
             rs.stride = nA_all;
@@ -991,7 +1266,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
             pool_cap = std::max<uint64_t>(1ull << 22, 32 * nnz_sum + (4ull << 20));
             // a fixed region gives the pool at most a third of what is left;
             // roots that find no room are rebuilt into an exactly sized pool
-            if (ex.fixed) pool_cap = std::max<uint64_t>(1, std::min<uint64_t>(pool_cap, mem.room() / 3 / 8));
+            if (ex.fixed || mem.cap) pool_cap = std::max<uint64_t>(1, std::min<uint64_t>(pool_cap, mem.room() / 3 / 8));
             uint64_t *d_off;
             BC_HIP(mem.get(&d_off, total_roots));
             BC_HIP(mem.get(&d_pool_fused, pool_cap));
@@ -1044,6 +1319,25 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
             spec_jobs[i] = {a};
         }
     }
+    // Served batches: a job that the cost model says cannot finish before its
+    // deadline, even at the best rate seen for its depth, is refused here,
+    // before the enumeration, instead of holding the device until it expires.
+    std::vector<char> refused(nj, 0);
+    if (short_first) {
+        RateBook &rb = rate_book();
+        std::lock_guard<std::mutex> lk(rb.mu);
+        const uint64_t now = bcint::steady_ns();
+        for (uint32_t j : cj) {
+            const uint64_t dl = specs[jobs[j].spec].deadline_ns;
+            const uint32_t pA = jobs[j].pA;
+            if (!job_live[j] || !dl || pA < 3 || pA > 32 || rb.ns_per_unit[pA] <= 0) continue;
+            const double left = dl > now ? (double)(dl - now) : 0.0;
+            if ((double)jobs[j].weight * rb.ns_per_unit[pA] > kRefuseMargin * left) {
+                refused[j] = 1;
+                job_live[j] = 0;
+            }
+        }
+    }
     struct Plan {
         uint32_t c;  // index into cj / cjobs
         uint32_t root, k, w1;
@@ -1084,6 +1378,61 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         for (size_t r = 0; r < plan.size(); ++r) sorted[r] = plan[ord[r]];
         plan.swap(sorted);
     }
+    // Roots of the global-set path: all of them with sets = HTB or SORTED;
+    // with local bitmaps, those with more neighbours than bitmap_bits (they
+    // take HTB).  They keep their place in the cost order.
+    std::vector<Plan> splan;
+    const uint32_t set_mode = sets_opt == BC_SETS_SORTED ? bcdev::SETS_SORTED : bcdev::SETS_HTB;
+    if (sets_opt != BC_SETS_LOCAL_BITMAP || bitmap_bits) {
+        std::vector<Plan> keep;
+        for (const Plan &pl : plan) {
+            const HostJob &hj = jobs[cj[pl.c]];
+            const Side &A = specs[hj.spec].g->side[hj.anchor];
+            const uint64_t du = A.h_ptr[pl.root + 1] - A.h_ptr[pl.root];
+            const bool to_sets = sets_opt != BC_SETS_LOCAL_BITMAP || du > bitmap_bits;
+            (to_sets ? splan : keep).push_back(pl);
+        }
+        plan.swap(keep);
+    }
+    std::vector<bcdev::SetRoot> sroots(splan.size());
+    uint64_t set_tasks = 0, set_ids = 0, set_slab_need = 64;
+    if (!splan.empty()) {
+        if (set_mode == bcdev::SETS_HTB) {
+            std::vector<char> done(cj.size(), 0);
+            for (const Plan &pl : splan) {
+                if (done[pl.c]) continue;
+                done[pl.c] = 1;
+                const HostJob &hj = jobs[cj[pl.c]];
+                bc_graph *g = const_cast<bc_graph *>(specs[hj.spec].g);   // the HTB is a cache of the graph
+                if (bc_status e = ensure_htb(g, hj.anchor, st)) return e;
+                const Side &A = g->side[hj.anchor];
+                cjobs[pl.c].htb_off = A.d_htb_off;
+                cjobs[pl.c].htb_idx = A.d_htb_idx;
+                cjobs[pl.c].htb_val = A.d_htb_val;
+            }
+            BC_HIP(hipMemcpyAsync(d_cjobs, cjobs.data(), cjobs.size() * sizeof(bcdev::Job), hipMemcpyHostToDevice, st));
+        }
+        for (size_t r = 0; r < splan.size(); ++r) {
+            const Plan &pl = splan[r];
+            const HostJob &hj = jobs[cj[pl.c]];
+            const Side &A = specs[hj.spec].g->side[hj.anchor];
+            const uint32_t pA = cjobs[pl.c].pA;
+            bcdev::SetRoot &a = sroots[r];
+            a.id_off = set_ids;
+            a.task_begin = set_tasks;
+            a.job = pl.c;
+            a.root = pl.root;
+            a.k = pl.k;
+            a.n_tasks = pl.k - (pA - 2);
+            set_ids += pl.k;
+            set_tasks += a.n_tasks;
+            // per task: one set and one kept list per level 2 .. pA-1, each
+            // set at most the root's own row (words or ids), each list at most k ids
+            const uint64_t mu = set_mode == bcdev::SETS_HTB ? A.h_htb_off[pl.root + 1] - A.h_htb_off[pl.root]
+                                                            : A.h_ptr[pl.root + 1] - A.h_ptr[pl.root];
+            set_slab_need = std::max<uint64_t>(set_slab_need, (uint64_t)pA * (mu + pl.k / 2 + 2) + 16);
+        }
+    }
     std::vector<bcdev::ActiveRoot> aroots(plan.size());
     uint64_t pool_words = 0, tasks = 0, slab_need = 64;
     // rows already built by the fused kernel, unless some root found no room
@@ -1116,6 +1465,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan0).count();
 
     tm.mark(2, st);
+    const uint64_t t_enum0 = bcint::steady_ns();
     if (!plan.empty()) {
         bcdev::ActiveRoot *d_roots;
         uint64_t *d_pool = d_pool_fused;
@@ -1128,11 +1478,29 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
                                             d_queue + 1, d_slots, st));
         }
         tm.mark(3, st);
+        // Subtask ring of the runtime split (queries with p_A >= 5): up to 4M
+        // entries of 16 bytes, cleared before the launch.
+        uint32_t split_cap = 0;
+        uint4 *d_ring = nullptr;
+        unsigned long long *d_sub = nullptr;
+        bool any_deep = false;
+        for (const bcdev::ActiveRoot &a : aroots) any_deep = any_deep || cjobs[a.job].pA >= 5;
+        if (any_deep && split_rows != 0 && split_rows != 0xffffffffu) {
+            uint64_t cap = 1ull << 22;
+            if (ex.fixed || mem.cap) cap = std::min<uint64_t>(cap, mem.room() / 4 / sizeof(uint4));
+            if (cap >= 1024) {
+                BC_HIP(mem.get(&d_ring, cap));
+                BC_HIP(mem.get(&d_sub, 2));
+                BC_HIP(fill_u32((uint32_t *)d_ring, cap * 4, 0u, st));
+                BC_HIP(fill_u32((uint32_t *)d_sub, 4, 0u, st));
+                split_cap = (uint32_t)cap;
+            }
+        }
         // Enumeration grid: waves_per_cu wavefronts per CU; each wave owns a
         // slab big enough for the deepest task of this plan.
         uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ncu * waves_per_cu / bcdev::kWavesPerBlock);
         uint64_t slab_budget = 64ull << 30;   // bytes of HBM for all slabs
-        if (ex.fixed) slab_budget = std::min(slab_budget, mem.room() > 512 ? mem.room() - 512 : 0);
+        slab_budget = std::min(slab_budget, mem.room() > 512 ? mem.room() - 512 : 0);
         while (blocks > 1 && (uint64_t)blocks * bcdev::kWavesPerBlock * slab_need * 8 > slab_budget) blocks /= 2;
         uint64_t *d_slab;
         BC_HIP(mem.get(&d_slab, (uint64_t)blocks * bcdev::kWavesPerBlock * slab_need));
@@ -1147,7 +1515,11 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         prm.task_chunk = roots_per_wave ? roots_per_wave
                                         : (tasks >= 1024ull * blocks * bcdev::kWavesPerBlock ? 8u : 4u);
         prm.triple = switch_depth == 2 ? 0u : 1u;
-        prm.split_rows = split_rows;
+        prm.split_rows = split_rows ? split_rows : 256u;
+        prm.split_cap = split_cap;
+        prm.ring = d_ring;
+        prm.sub_head = d_sub;
+        prm.sub_tail = d_sub ? d_sub + 1 : nullptr;
         prm.pool = d_pool;
         prm.slab = d_slab;
         prm.slab_words = slab_need;
@@ -1159,11 +1531,61 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
     } else {
         tm.mark(3, st);
     }
+    if (!splan.empty()) {
+        // global-set path: candidate ids, then the enumeration over them
+        bcdev::SetRoot *d_sroots;
+        uint32_t *d_ids;
+        BC_HIP(mem.get(&d_sroots, sroots.size()));
+        BC_HIP(mem.get(&d_ids, set_ids));
+        BC_HIP(hipMemcpyAsync(d_sroots, sroots.data(), sroots.size() * sizeof(bcdev::SetRoot), hipMemcpyHostToDevice,
+                              st));
+        BC_HIP(bcdev::launch_cand_ids(d_cjobs, d_sroots, (uint32_t)sroots.size(), d_ids, rs,
+                                      (uint32_t)std::min<uint64_t>(sroots.size(), std::max<uint32_t>(rs_blocks, 1)),
+                                      d_queue + 8, d_slots, st));
+        uint32_t blocks = (uint32_t)std::max<uint64_t>(1, (uint64_t)ncu * waves_per_cu / bcdev::kWavesPerBlock);
+        uint64_t slab_budget = 64ull << 30;
+        slab_budget = std::min(slab_budget, mem.room() > 512 ? mem.room() - 512 : 0);
+        while (blocks > 1 && (uint64_t)blocks * bcdev::kWavesPerBlock * set_slab_need * 8 > slab_budget) blocks /= 2;
+        uint64_t *d_sslab;
+        BC_HIP(mem.get(&d_sslab, (uint64_t)blocks * bcdev::kWavesPerBlock * set_slab_need));
+        bcdev::SetParams sp{};
+        sp.jobs = d_cjobs;
+        sp.roots = d_sroots;
+        sp.n_roots = (uint32_t)sroots.size();
+        sp.task_chunk = roots_per_wave ? roots_per_wave : 4u;
+        sp.n_tasks = set_tasks;
+        sp.ids = d_ids;
+        sp.mode = set_mode;
+        sp.instrument = instrument ? 1u : 0u;
+        sp.pure_dfs = BC_OPT(opts, pure_dfs, 0u) ? 1u : 0u;
+        sp.slab = d_sslab;
+        sp.slab_words = set_slab_need;
+        sp.queue = d_queue + 9;
+        sp.slots = d_slots;
+        BC_HIP(bcdev::launch_enumerate_sets(sp, blocks, st));
+        tasks += set_tasks;
+    }
     tm.mark(4, st);
     std::vector<bcdev::Slot> hs(nj);
     BC_HIP(hipMemcpyAsync(hs.data(), d_slots, nj * sizeof(bcdev::Slot), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
     read_back = true;
+    if (short_first) {
+        // learn from a served batch that enumerated exactly one job to the end
+        int only = -1, live = 0;
+        for (uint32_t j : cj)
+            if (job_live[j] && jobs[j].pA >= 3) {
+                only = (int)j;
+                ++live;
+            }
+        if (live == 1 && jobs[only].weight > 0 && !(hs[only].flags & (bcdev::FLAG_TIMEOUT | bcdev::FLAG_CAPACITY))) {
+            const double ns = (double)(bcint::steady_ns() - t_enum0) / (double)jobs[only].weight;
+            RateBook &rb = rate_book();
+            std::lock_guard<std::mutex> lk(rb.mu);
+            double &r = rb.ns_per_unit[jobs[only].pA];
+            r = r > 0 ? std::min(r, ns) : ns;
+        }
+    }
 
     // 6. Results.  Candidate jobs for the same spec: only the live one counts.
     bc_status overall = BC_OK;
@@ -1174,7 +1596,10 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
             out[i] = bc_u128{0, 0};
             continue;
         }
-        if (s.flags & bcdev::FLAG_TIMEOUT) {
+        if (refused[j]) {
+            item_status[i] = BC_E_REJECTED;
+            g_last_error = "refused: the cost model puts the count past its deadline";
+        } else if (s.flags & bcdev::FLAG_TIMEOUT) {
             item_status[i] = BC_E_TIMEOUT;
             g_last_error = "time limit reached before the count finished";
         } else if (s.flags & bcdev::FLAG_OVERFLOW) {
@@ -1203,6 +1628,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         stats->tasks = tasks;
         stats->candidate_edges = cand_edges;
         stats->row_words = pool_words;
+        stats->scratch_bytes = mem.total;
         for (size_t i = 0; i < ns; ++i) {
             const bcdev::Slot &sl = hs[spec_jobs[i][0]];
             stats->pair_ops += sl.pair_ops;
@@ -1310,6 +1736,17 @@ extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_
     return s;
 }
 
+extern "C" bc_status bc_scratch_estimate(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts,
+                                         uint64_t *bytes)
+{
+    g_last_error.clear();
+    if (!g || !bytes) return set_error(BC_E_INVALID_ARG, "bc_scratch_estimate: NULL argument");
+    if (bc_status s = check_pq(p, q)) return s;
+    if (bc_status s = check_opts(opts)) return s;
+    *bytes = bcint::estimate_scratch_bytes(g, p, q, (opts && opts->waves_per_cu) ? opts->waves_per_cu : 12u);
+    return BC_OK;
+}
+
 extern "C" bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
                                    const bc_opts *base, bc_opts *tuned)
 {
@@ -1326,32 +1763,58 @@ extern "C" bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t
     const size_t step = std::max<size_t>(1, n / want);
     std::vector<const bc_graph *> sg;
     std::vector<uint32_t> sp, sq;
+    bool deep = false;   // some sampled item can take the runtime split (anchor depth min(p, q) >= 5)
     for (size_t i = 0; i < n; i += step) {
         sg.push_back(graphs[i]);
         sp.push_back(p[i]);
         sq.push_back(q[i]);
+        deep = deep || std::min(p[i], q[i]) >= 5;
     }
     std::vector<bc_u128> out(sg.size());
     std::vector<bc_status> st(sg.size());
-    const uint32_t waves[3] = {12, 8, 4};
-    const uint32_t lds[2] = {0, 256};   // 0 = the default arena
-    double best = -1.0;
-    for (uint32_t w : waves)
-        for (uint32_t l : lds) {
-            bc_opts c = b;
-            c.waves_per_cu = w;
-            c.lds_words = l;
-            const uint64_t t0 = bcint::steady_ns();
-            bc_status s = bc_count_batch(sg.data(), sp.data(), sq.data(), sg.size(), &c, out.data(), st.data(), nullptr);
-            if (s != BC_OK) return s;
-            double t = (double)(bcint::steady_ns() - t0);
-            for (bc_status x : st)
-                if (x != BC_OK && b.timeout_ms) t += (double)b.timeout_ms * 1e6;
-            if (best < 0 || t < best) {
+    // sample time of one schedule (items over the base's time limit count as the whole limit)
+    auto timed = [&](const bc_opts &c, double *t) -> bc_status {
+        const uint64_t t0 = bcint::steady_ns();
+        bc_status s = bc_count_batch(sg.data(), sp.data(), sq.data(), sg.size(), &c, out.data(), st.data(), nullptr);
+        if (s != BC_OK) return s;
+        *t = (double)(bcint::steady_ns() - t0);
+        for (bc_status x : st)
+            if (x != BC_OK && b.timeout_ms) *t += (double)b.timeout_ms * 1e6;
+        return BC_OK;
+    };
+    // Coordinate descent: each knob in turn takes the value with the shortest
+    // sample time, the knobs before it at their chosen values and the ones
+    // after it at the base's.  A warm-up run first (first-launch costs).
+    bc_opts cur = b;
+    double best = 0;
+    if (bc_status s = timed(cur, &best)) return s;
+    if (bc_status s = timed(cur, &best)) return s;
+    struct Knob {
+        uint32_t bc_opts::*field;
+        std::vector<uint32_t> values;
+    };
+    std::vector<Knob> knobs = {
+        {&bc_opts::waves_per_cu, {12, 8, 4}},
+        {&bc_opts::lds_words, {0, 256}},
+        {&bc_opts::roots_per_wave, {0, 2, 4, 16}},
+        {&bc_opts::switch_depth, {3, 2}},
+    };
+    if (deep) knobs.push_back({&bc_opts::split_rows, {0, 64, 256, 1024}});
+    for (const Knob &kn : knobs) {
+        const uint32_t start = cur.*kn.field;
+        for (uint32_t v : kn.values) {
+            if (v == start) continue;
+            bc_opts c = cur;
+            c.*kn.field = v;
+            double t = 0;
+            if (bc_status s = timed(c, &t)) return s;
+            if (t < best) {
                 best = t;
-                *tuned = c;
+                cur = c;
             }
         }
+    }
+    *tuned = cur;
     return BC_OK;
 }
 
@@ -1390,15 +1853,39 @@ bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 
     return s;
 }
 
-uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q)
+// Admission estimate of the device scratch of one count of g at (p, q) with
+// waves_per_cu wavefronts per CU: the sizes run_jobs takes, each per-root
+// quantity at its bound over the graph (candidates k <= min(n_A - 1, max
+// wedges), row words W1 <= ceil(max degree / 64)), the worse of the two
+// anchors, and the row pool twice (a rebuild after an overflow).  The
+// enumeration slabs are charged at most 8 GiB: a call capped at the estimate
+// (bc_opts.scratch_cap_bytes, as the server does) shrinks its grid to fit.
+uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q, uint32_t waves_per_cu)
 {
-    // candidate-pass scratch (3 u32 arrays per block over the anchor side),
-    // the row pool of the fused per-root kernel (32 words per edge plus
-    // 32 MiB) and a share of the enumeration slabs.
-    (void)q;
-    const uint64_t n = std::max(g->side[0].n, g->side[1].n);
-    const uint64_t blocks = 2ull * 256;
-    return blocks * n * 12 + 256 * g->nnz + (32ull << 20) + (uint64_t)std::max<uint32_t>(p, 1) * (64ull << 20);
+    const uint64_t ncu = (uint64_t)cu_count(g->device);
+    const uint64_t waves =
+        std::max<uint64_t>(bcdev::kWavesPerBlock, ncu * std::min(12u, std::max(1u, waves_per_cu)));
+    const Side &s0 = g->side[0], &s1 = g->side[1];
+    const uint64_t n_all = std::max(s0.n, s1.n);
+    const uint64_t pool = 8 * std::max<uint64_t>(1ull << 22, 32 * g->nnz + (4ull << 20));
+    uint64_t fixed = (1ull << 20) + 32ull * (std::max(s0.max_deg, s1.max_deg) + 1)   // jobs, tables, slots
+                     + 2 * ncu * n_all * 12                                          // candidate counters
+                     + 48 * (s0.n + s1.n)                                            // per-root arrays
+                     + 2 * pool;
+    uint64_t worst = 0;
+    for (int a = 0; a < 2; ++a) {
+        const uint32_t pA = a == 0 ? p : q;
+        const Side &A = g->side[a];
+        if (pA < 3) continue;
+        const double k = (double)std::min<uint64_t>(A.n ? A.n - 1 : 0, A.max_wedges);
+        const double w1 = (double)((A.max_deg + 63) / 64);
+        const double need = 10 * w1 + k / 2 + 1 + (pA >= 5 ? 20521.0 : 0.0) +
+                            (pA >= 4 ? (double)(pA - 3) * std::max(0.0, k - 1) * w1 : 0.0) + 8;
+        const double slab = std::min((double)(8ull << 30), (double)waves * need * 8);
+        const uint64_t ring = pA >= 5 ? (64ull << 20) + 64 : 0;
+        worst = std::max<uint64_t>(worst, (uint64_t)slab + ring);
+    }
+    return fixed + worst;
 }
 
 int graph_device(const bc_graph *g) { return g->device; }

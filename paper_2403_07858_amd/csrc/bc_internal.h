@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "bc.h"
+#include "bc_server.h"
 
 namespace bcint {
 
@@ -20,9 +21,31 @@ uint64_t steady_ns();
 // n counts through one batched device pass; per-query status in status[i].
 bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 *out, bc_status *status);
 
-// Admission estimate of the device scratch one count of g may need.
-uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q);
+// Admission estimate of the device scratch one count of g at (p, q) takes when
+// run with waves_per_cu wavefronts per CU under a cap of that size.
+uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q, uint32_t waves_per_cu);
 
 int graph_device(const bc_graph *g);
+
+// What the serving scheduler needs from the device side.  The library uses
+// hip_server_backend(); the scheduler itself touches no device API, so it can
+// also run against a host-only stand-in (the CPU stress test does).
+struct ServerBackend {
+    // one batch of counts on `stream` (opts->stream); per-query status and value
+    bc_status (*count)(const Query *qs, size_t n, const bc_opts *opts, bc_u128 *out, bc_status *status);
+    // admission estimate of the device scratch of one count on waves_per_cu wavefronts per CU
+    uint64_t (*estimate)(const bc_graph *g, uint32_t p, uint32_t q, uint32_t waves_per_cu);
+    int (*device)(const bc_graph *g);
+    // a stream of the worker's own on `device` (NULL if none could be made), and its release
+    void *(*stream_create)(int device);
+    void (*stream_destroy)(void *stream);
+    // default memory budget: half of the device memory free after the caches are trimmed
+    uint64_t (*default_budget)();
+};
+
+const ServerBackend *hip_server_backend();
+
+// bc_server_create with an explicit backend.
+bc_status server_create(const bc_server_opts *opts, const ServerBackend *backend, bc_server **out);
 
 }  // namespace bcint

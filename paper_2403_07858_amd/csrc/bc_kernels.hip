@@ -1590,10 +1590,54 @@ __device__ __forceinline__ void count_pairs(Counters &ct, uint32_t m, uint32_t W
 
 __device__ __forceinline__ uint64_t cycles() { return __builtin_amdgcn_s_memtime(); }
 
-// One (root, second vertex) task: the node {u, c_i} of the search tree.
-__device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, const uint64_t *pool,
-                         Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument,
-                         bool triple, bool *cap_fail, bool *timed_out)
+// Runtime split of heavy tasks: a task whose level-2 block keeps more than
+// `rows` rows queues one subtask per kept row in a ring that wavefronts drain
+// once the task queue is empty (runtime load balancing, Section V-C).
+struct SplitCtx {
+    uint4 *ring;                    // {root index, i, j, ready}; ready is stored last
+    unsigned long long *tail;       // entries reserved so far
+    uint32_t cap;                   // ring entries
+    uint32_t rows;                  // split threshold on the kept rows
+    uint32_t root_idx;              // index of the task's root in the active-root list
+};
+
+constexpr uint32_t kNoJ = 0xffffffffu;   // "no third vertex": a (root, second vertex) task
+
+// Reserves n consecutive ring entries (lane 0 decides, every lane learns);
+// ~0 when the ring cannot hold them.
+__device__ unsigned long long ring_reserve(const SplitCtx &sp, uint32_t n)
+{
+    unsigned long long got = ~0ull;
+    if (lane_id() == 0) {
+        unsigned long long cur = __hip_atomic_load(sp.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (cur + n <= sp.cap) {
+            if (__hip_atomic_compare_exchange_strong(sp.tail, &cur, cur + n, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                got = cur;
+                break;
+            }
+        }
+    }
+    return bcast64(got, 0);
+}
+
+// Publishes one ring entry: the payload first, then the ready word with
+// release order, so that a reader that sees ready also sees the payload.
+__device__ __forceinline__ void ring_put(uint4 *e, uint32_t r, uint32_t i, uint32_t j)
+{
+    e->x = r;
+    e->y = i;
+    e->z = j;
+    __hip_atomic_store(&e->w, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One task: the node {u, c_i} of the search tree (j == kNoJ), or, for a
+// subtask of a split task, the node {u, c_i, c_j} (its common neighbours are
+// rows i and j ANDed, its candidates are the rows after j, and pA is one less:
+// the node is then handled exactly like a task of a query one level shallower).
+__device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, uint32_t j, uint32_t pA,
+                         const uint64_t *pool, Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct,
+                         bool instrument, bool triple, const SplitCtx *sp, bool *cap_fail, bool *timed_out)
 {
     const uint32_t ln = lane_id();
     const uint32_t u = rt.root;
@@ -1601,11 +1645,12 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     const uint32_t W1 = (du + 63) >> 6;
     const uint32_t k = rt.k;
     glb_u64 *base = (glb_u64 *)(pool + rt.pool_off);   // the root's rows (global: typed loads)
-    const uint32_t q = jb.qA, pA = jb.pA;
+    const uint32_t q = jb.qA;
     uint64_t t0 = instrument ? cycles() : 0;
 
-    const uint32_t rem = k - i - 1;
-    if (pA == 3 && W1 <= kTileWords && du <= jb.n_u28 && table_ready(tb, jb, jidx, du + 1)) {
+    const uint32_t s = j == kNoJ ? i : j;   // the candidates are the rows after s
+    const uint32_t rem = k - s - 1;
+    if (j == kNoJ && pA == 3 && W1 <= kTileWords && du <= jb.n_u28 && table_ready(tb, jb, jidx, du + 1)) {
         // the root's leaves {u, c_a, c_b} are the pair sum over its rows:
         // task i = 16 I takes row block I on the matrix cores, the root's
         // other tasks have nothing left to do
@@ -1638,7 +1683,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     uint64_t *nzt = nullptr;
     if (W1 == 1) {
         // one-word root: nothing to scan or tabulate
-        const uint64_t x = base[i];
+        const uint64_t x = base[i] & (j == kNoJ ? ~0ull : base[j]);
         const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
         const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
         s0 = ((uint64_t)hi << 32) | lo;
@@ -1654,7 +1699,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         uint64_t *s2 = arena_alloc(ar, 2ull * W1, cap_fail);
         if (!s2) return;
         uint64_t *pre = s2 + W1;
-        for (uint32_t w = ln; w < W1; w += kWaveSize) s2[w] = base[(uint64_t)w * k + i];
+        for (uint32_t w = ln; w < W1; w += kWaveSize)
+            s2[w] = base[(uint64_t)w * k + i] & (j == kNoJ ? ~0ull : base[(uint64_t)w * k + j]);
         wave_sync();
         uint32_t running = 0;
         for (uint32_t x0 = 0; x0 < W1; x0 += kWaveSize) {
@@ -1719,7 +1765,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
 
     if (pA == 3) {
         // Leaves {u, c_i, c_b}: sum of C(|S2 n row_b|, q).
-        for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
+        for (uint32_t b0 = s + 1; b0 < k; b0 += kWaveSize) {
             const uint32_t b = b0 + ln;
             if (b < k) {
                 uint32_t n = 0;
@@ -1749,7 +1795,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         // chunks are loaded together before any of them is filtered.
         glb_u64 *r0 = base + (uint64_t)w0 * k;
         glb_u64 *r1 = base + (uint64_t)(nz > 1 ? w1 : w0) * k;
-        for (uint32_t b0 = i + 1; b0 < k; b0 += kFilterDepth * kWaveSize) {
+        for (uint32_t b0 = s + 1; b0 < k; b0 += kFilterDepth * kWaveSize) {
             uint64_t x0[kFilterDepth], x1[kFilterDepth];
 #pragma unroll
             for (uint32_t c = 0; c < kFilterDepth; ++c) {
@@ -1777,10 +1823,10 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         // those, 64 per step, so that no lane packs a row that was dropped.
         uint32_t *kept = (uint32_t *)arena_alloc(ar, (rem + 1) / 2, cap_fail);
         if (!kept) return;
-        for (uint32_t b0 = i + 1; b0 < k; b0 += kWaveSize) {
+        for (uint32_t b0 = s + 1; b0 < k; b0 += kWaveSize) {
             const uint32_t b = b0 + ln;
             const bool valid = b < k;
-            const uint32_t bb = valid ? b : i;
+            const uint32_t bb = valid ? b : s;
             uint32_t n = 0;
             for (uint32_t e = 0; e < nz; ++e) {
                 const uint32_t w = (uint32_t)nzt[8ull * e + 7];
@@ -1795,7 +1841,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         for (uint32_t c0 = 0; c0 < m2; c0 += kWaveSize) {
             const uint32_t idx = c0 + ln;
             const bool live = idx < m2;
-            const uint32_t bb = live ? kept[idx] : i;
+            const uint32_t bb = live ? kept[idx] : s;
             if (nz == W2) {
                 // S2's nonzero words are already as few as its bits need: the
                 // masked words are the compacted row (word e = S2 word e's bits)
@@ -1849,6 +1895,41 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         t0 = t1;
     }
     if (m2 < pA - 2) return;
+    if (sp && j == kNoJ && pA >= 5 && m2 > sp->rows) {
+        // Heavy task: queue the nodes {u, c_i, c_b} of its kept rows b as
+        // subtasks.  The kept rows are found again (the same integer test
+        // as above, so the same m2 rows); entries the ring cannot take are
+        // not reserved and the task continues here instead.
+        const unsigned long long at = ring_reserve(*sp, m2);
+        if (at != ~0ull) {
+            uint32_t put = 0;
+            for (uint32_t b0 = s + 1; b0 < k; b0 += kWaveSize) {
+                const uint32_t b = b0 + ln;
+                const uint32_t bb = b < k ? b : s;
+                uint32_t n = 0;
+                if (nz <= 2) {
+                    if (nz > 0) n += __popcll(s0 & base[(uint64_t)w0 * k + bb]);
+                    if (nz > 1) n += __popcll(s1 & base[(uint64_t)w1 * k + bb]);
+                } else {
+                    for (uint32_t e = 0; e < nz; ++e) {
+                        const uint32_t w = (uint32_t)nzt[8ull * e + 7];
+                        n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + bb]);
+                    }
+                }
+                const bool keep = b < k && n >= q;
+                const uint64_t mask = __ballot(keep);
+                const uint32_t slot = put + mbcnt64(mask);
+                if (keep && slot < m2) ring_put(sp->ring + at + slot, sp->root_idx, i, b);
+                put += (uint32_t)__popcll(mask);
+            }
+            // (put == m2; should it differ, the reserved entries left over are
+            // published as empty so that no reader waits on them)
+            for (uint32_t x = put + ln; x < m2; x += kWaveSize) ring_put(sp->ring + at + x, sp->root_idx, i, kNoJ);
+            if (put != m2) *cap_fail = true;
+            if (instrument) ct.filter_words += (unsigned long long)rem * nz;
+            return;
+        }
+    }
     if (pA == 4) {
         const uint32_t G = pair_sum(blk2, ar.holds(blk2), rem, m2, W2, s2n, jb, jidx, tb, acc);
         if (instrument) count_pairs(ct, m2, W2, G);
@@ -2011,13 +2092,30 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     acc.t = 0;
     Counters ct{};
     uint32_t cur_job = 0xffffffffu;
+    // With splitting on, a wavefront counts itself as a producer (the high
+    // bits of the queue word) in the same atomic that pops its chunk, and
+    // leaves that count, with release order after its ring entries, once the
+    // chunk is done; the drain below uses the count to know when no more
+    // subtasks can appear.
+    const bool split = prm.split_cap != 0;
+    const unsigned long long kProducer = 1ull << 40, kPopMask = kProducer - 1;
+    SplitCtx sp;
+    sp.ring = prm.ring;
+    sp.tail = prm.sub_tail;
+    sp.cap = prm.split_cap;
+    sp.rows = prm.split_rows;
+    sp.root_idx = 0;
     for (;;) {
         // pop task_chunk consecutive tasks; only the first needs the root
         // search, the rest advance through the (contiguous) task ranges
         unsigned long long t0 = 0;
-        if (ln == 0) t0 = atomicAdd(prm.queue, (unsigned long long)prm.task_chunk);
-        t0 = bcast64(t0, 0);
-        if (t0 >= prm.n_tasks) break;
+        if (ln == 0) t0 = atomicAdd(prm.queue, (unsigned long long)prm.task_chunk + (split ? kProducer : 0ull));
+        t0 = bcast64(t0, 0) & kPopMask;
+        if (t0 >= prm.n_tasks) {
+            if (split && ln == 0)
+                __hip_atomic_fetch_add(prm.queue, 0ull - kProducer, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
         const unsigned long long t_end = min(t0 + prm.task_chunk, (unsigned long long)prm.n_tasks);
         // root owning task t0: largest r with roots[r].task_begin <= t0
         uint32_t r = 0, hi = prm.n_roots;
@@ -2035,12 +2133,77 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             }
             const Job jb = prm.jobs[rt.job];
             bool cap_fail = false, timed_out = past_deadline(jb.deadline);
+            sp.root_idx = r;
             if (!timed_out)
-                run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct,
-                         instrument, prm.triple != 0, &cap_fail, &timed_out);
+                run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), kNoJ, jb.pA, prm.pool, arena, stack, tb, acc,
+                         ct, instrument, prm.triple != 0, split ? &sp : nullptr, &cap_fail, &timed_out);
             if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
             if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
         }
+        if (split && ln == 0)
+            __hip_atomic_fetch_add(prm.queue, 0ull - kProducer, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // Drain the subtask ring.  Each wavefront claims one entry index at a
+    // time.  It waits while the entry is reserved but not yet published (its
+    // producer is running and publishes it right after the reservation), or
+    // while the index is past the reserved entries but some producer is still
+    // running a chunk (it may reserve more).  Once no producer is left, the
+    // reserved count is final: an index at or past it, or past the ring, will
+    // never be filled and the wavefront is done.  Producers only run popped
+    // chunks, so every wait ends when they finish their (finite) tasks.
+    while (split) {
+        unsigned long long h = 0;
+        if (ln == 0) h = atomicAdd(prm.sub_head, 1ull);
+        h = bcast64(h, 0);
+        uint32_t state = 0;   // 0 wait, 1 entry ready, 2 done
+        for (;;) {
+            if (ln == 0) {
+                if (h >= prm.split_cap) {
+                    state = 2;
+                } else {
+                    const unsigned long long tl =
+                        __hip_atomic_load(prm.sub_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (h < tl) {
+                        if (__hip_atomic_load(&prm.ring[h].w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                            state = 1;
+                    } else {
+                        const unsigned long long v =
+                            __hip_atomic_load(prm.queue, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((v >> 40) == 0 &&
+                            h >= __hip_atomic_load(prm.sub_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT))
+                            state = 2;
+                    }
+                }
+            }
+            state = (uint32_t)__builtin_amdgcn_readfirstlane(state);
+            if (state != 0) break;
+            __builtin_amdgcn_s_sleep(4);
+        }
+        if (state == 2) break;
+        uint32_t er = 0, ei = 0, ej = 0;
+        if (ln == 0) {
+            const uint4 e = prm.ring[h];
+            er = e.x;
+            ei = e.y;
+            ej = e.z;
+        }
+        er = (uint32_t)__builtin_amdgcn_readfirstlane(er);
+        ei = (uint32_t)__builtin_amdgcn_readfirstlane(ei);
+        ej = (uint32_t)__builtin_amdgcn_readfirstlane(ej);
+        if (ej == kNoJ) continue;   // an empty entry
+        const ActiveRoot rt = prm.roots[er];
+        if (rt.job != cur_job) {
+            if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
+            cur_job = rt.job;
+        }
+        const Job jb = prm.jobs[rt.job];
+        bool cap_fail = false, timed_out = past_deadline(jb.deadline);
+        if (!timed_out)
+            run_task(jb, rt.job, rt, ei, ej, jb.pA - 1, prm.pool, arena, stack, tb, acc, ct, instrument,
+                     prm.triple != 0, nullptr, &cap_fail, &timed_out);
+        if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
+        if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
     }
     if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
 }
@@ -2049,6 +2212,393 @@ hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_
 {
     if (prm.n_tasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_enumerate, dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Global-set path: the search of Algorithm 1 with its intersections done on
+// the graph's own adjacency instead of per-root local bitmaps.  Candidate
+// sets C_L are id lists; common-neighbour sets C_R are kept either as HTB
+// words (Section V-A: word index i and a 32-bit value whose bit j is B id
+// 32i + j) or as sorted id lists (word = id, value 1).  An intersection
+// C_R n N(c) is the two-phase HTB one: each element's index is
+// binary-searched in c's row, then the values are ANDed; with sorted lists
+// it is the plain binary search of Section III-B (a value of 1 on both
+// sides).  Lanes take 64 candidates at a time (Section IV's BFS over
+// siblings); descending to a child intersects the node's set with the
+// child's row, the wave's lanes taking its elements.
+
+// k_cand_ids: for every global-set root, the ids w > u with |N(u) n N(w)| >=
+// qA (dense per-block counters as in k_cand_count), in the order met.
+__global__ __launch_bounds__(kBlockThreads) void k_cand_ids(const Job *jobs, const SetRoot *roots, uint32_t n_roots,
+                                                            uint32_t *ids, RootScratch sc, unsigned long long *queue,
+                                                            Slot *slots)
+{
+    __shared__ unsigned long long s_item;
+    __shared__ uint32_t s_nt, s_k;
+    uint32_t *cnt = sc.cnt + (uint64_t)blockIdx.x * sc.stride;
+    uint32_t *touched = sc.touched + (uint64_t)blockIdx.x * sc.stride;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            s_item = atomicAdd(queue, 1ull);
+            s_nt = 0;
+            s_k = 0;
+        }
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= n_roots) break;
+        const SetRoot rt = roots[item];
+        const Job jb = jobs[rt.job];
+        const uint32_t u = rt.root;
+        const uint64_t ub = jb.ptrA[u];
+        const uint32_t du = (uint32_t)(jb.ptrA[u + 1] - ub);
+        oriented_wedges(jb, u, ub, du, [&](uint32_t, uint32_t w) {
+            if (atomicAdd(&cnt[w], 1u) == 0u) touched[atomicAdd(&s_nt, 1u)] = w;
+        });
+        __syncthreads();
+        const uint32_t nt = s_nt;
+        for (uint32_t t = tid; t < nt; t += kBlockThreads) {
+            const uint32_t w = touched[t];
+            const uint32_t c = atomicExch(&cnt[w], 0u);
+            if (c >= jb.qA) {
+                const uint32_t at = atomicAdd(&s_k, 1u);
+                if (at < rt.k) ids[rt.id_off + at] = w;
+            }
+        }
+        __syncthreads();
+        // the candidate pass counted the same set: a different size is an internal error
+        if (tid == 0 && s_k != rt.k) atomicOr(&slots[jb.slot].flags, FLAG_MISMATCH);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_cand_ids(const Job *jobs, const SetRoot *roots, uint32_t n_roots, uint32_t *ids,
+                           RootScratch scratch, uint32_t n_blocks, unsigned long long *queue, Slot *slots,
+                           hipStream_t stream)
+{
+    if (n_roots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cand_ids, dim3(n_blocks), dim3(kBlockThreads), 0, stream, jobs, roots, n_roots, ids,
+                       scratch, queue, slots);
+    return hipGetLastError();
+}
+
+template <uint32_t MODE>
+__device__ __forceinline__ uint64_t row_begin(const Job &jb, uint32_t x)
+{
+    return MODE == SETS_HTB ? jb.htb_off[x] : jb.ptrA[x];
+}
+template <uint32_t MODE>
+__device__ __forceinline__ uint32_t row_key(const Job &jb, uint64_t e)
+{
+    return MODE == SETS_HTB ? jb.htb_idx[e] : jb.adjA[e];
+}
+template <uint32_t MODE>
+__device__ __forceinline__ uint32_t row_val(const Job &jb, uint64_t e)
+{
+    return MODE == SETS_HTB ? jb.htb_val[e] : 1u;
+}
+
+// First position in [lo, hi) of x's row whose key is >= key.
+template <uint32_t MODE>
+__device__ __forceinline__ uint64_t row_lower_bound(const Job &jb, uint64_t lo, uint64_t hi, uint32_t key)
+{
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (row_key<MODE>(jb, mid) < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// |S n N(c)| in this lane, S = m packed elements (key << 32 | value) sorted
+// by key: each element is searched in what is left of c's row.
+template <uint32_t MODE>
+__device__ uint32_t set_count(const Job &jb, const uint64_t *S, uint32_t m, uint32_t c)
+{
+    uint64_t lo = row_begin<MODE>(jb, c);
+    const uint64_t hi = row_begin<MODE>(jb, c + 1);
+    uint32_t n = 0;
+    for (uint32_t e = 0; e < m && lo < hi; ++e) {
+        const uint64_t x = S[e];
+        const uint32_t key = (uint32_t)(x >> 32);
+        lo = row_lower_bound<MODE>(jb, lo, hi, key);
+        if (lo < hi && row_key<MODE>(jb, lo) == key) n += (uint32_t)__popc((uint32_t)x & row_val<MODE>(jb, lo));
+    }
+    return n;
+}
+
+// out = S n N(c), its elements with a nonzero value, in key order; the wave's
+// lanes take S's elements.  S is either a packed set (from_row false) or the
+// row of vertex `from` itself.  Returns the element count; *bits gets the
+// number of members.
+template <uint32_t MODE>
+__device__ uint32_t set_intersect(const Job &jb, const uint64_t *S, uint32_t m, bool from_row, uint32_t from,
+                                  uint32_t c, uint64_t *out, uint32_t *bits)
+{
+    const uint32_t ln = lane_id();
+    const uint64_t c0 = row_begin<MODE>(jb, c), c1 = row_begin<MODE>(jb, c + 1);
+    const uint64_t f0 = from_row ? row_begin<MODE>(jb, from) : 0;
+    uint32_t k = 0, nb = 0;
+    for (uint32_t e0 = 0; e0 < m; e0 += kWaveSize) {
+        const uint32_t e = e0 + ln;
+        uint64_t r = 0;
+        if (e < m) {
+            uint32_t key, val;
+            if (from_row) {
+                key = row_key<MODE>(jb, f0 + e);
+                val = row_val<MODE>(jb, f0 + e);
+            } else {
+                key = (uint32_t)(S[e] >> 32);
+                val = (uint32_t)S[e];
+            }
+            const uint64_t pos = row_lower_bound<MODE>(jb, c0, c1, key);
+            if (pos < c1 && row_key<MODE>(jb, pos) == key) {
+                const uint32_t w = val & row_val<MODE>(jb, pos);
+                if (w) r = ((uint64_t)key << 32) | w;
+            }
+        }
+        const bool keep = r != 0;
+        const uint64_t mask = __ballot(keep);
+        if (keep) out[k + mbcnt64(mask)] = r;
+        k += (uint32_t)__popcll(mask);
+        nb += (uint32_t)__popc((uint32_t)r);
+    }
+    wave_sync();
+    *bits = (uint32_t)wave_sum_u64(nb);
+    return k;
+}
+
+// |S n N(c)| with the wave's lanes over S's elements, for one candidate c
+// (the search without the BFS over siblings: each intersection in turn).
+template <uint32_t MODE>
+__device__ uint32_t set_count_wave(const Job &jb, const uint64_t *S, uint32_t m, uint32_t c)
+{
+    const uint32_t ln = lane_id();
+    const uint64_t c0 = row_begin<MODE>(jb, c), c1 = row_begin<MODE>(jb, c + 1);
+    uint32_t n = 0;
+    for (uint32_t e0 = 0; e0 < m; e0 += kWaveSize) {
+        const uint32_t e = e0 + ln;
+        if (e < m) {
+            const uint64_t x = S[e];
+            const uint32_t key = (uint32_t)(x >> 32);
+            const uint64_t pos = row_lower_bound<MODE>(jb, c0, c1, key);
+            if (pos < c1 && row_key<MODE>(jb, pos) == key) n += (uint32_t)__popc((uint32_t)x & row_val<MODE>(jb, pos));
+        }
+    }
+    return (uint32_t)wave_sum_u64(n);
+}
+
+constexpr uint32_t kSetLdsWords = 512;    // LDS part of each wave's arena in the global-set kernel
+constexpr uint32_t kSetLevels = 33;       // DFS levels (p_A <= 32)
+
+// One (root, second vertex) task of the global-set path: node {u, c_i},
+// then the DFS of Algorithm 1 down to |L| = pA - 1, whose candidates each
+// add C(|C_R n N(c)|, q).  Per level: the node's set S (arena), its
+// candidate list (a suffix of the parent's kept list), the kept list and a
+// cursor.
+// HYBRID: the 64 lanes take 64 siblings at a time (Section IV's BFS over
+// siblings); otherwise the siblings are visited one at a time and the lanes
+// share each intersection (the pure DFS the paper's ablation compares with).
+template <uint32_t MODE, bool HYBRID>
+__device__ void run_set_task(const Job &jb, const SetRoot &rt, uint32_t i, const uint32_t *ids, Arena ar,
+                             uint64_t *stk, Acc &acc, Counters &ct, bool instrument, bool *cap_fail, bool *timed_out)
+{
+    const uint32_t ln = lane_id();
+    const uint32_t q = jb.qA, pA = jb.pA, k = rt.k;
+    const uint32_t *cid = ids + rt.id_off;
+    const uint32_t u = rt.root;
+    // level-2 node {u, c_i}: S = N(u) n N(c_i), candidates c_{i+1} ..
+    const uint32_t mu = (uint32_t)(row_begin<MODE>(jb, u + 1) - row_begin<MODE>(jb, u));
+    uint64_t *S = arena_alloc(ar, mu, cap_fail);
+    if (!S) return;
+    uint32_t bits = 0;
+    uint32_t m = set_intersect<MODE>(jb, nullptr, mu, true, u, cid[i], S, &bits);
+    if (instrument) ct.filter_words += mu;
+    if (bits < q) return;
+    // Saved per level d while a child is explored (wave-private LDS stack):
+    // stk[8d] = S, [8d+1] = its element count, [8d+2] = kept list, [8d+3] =
+    // cursor << 32 | kept count, [8d+4] = candidates, [8d+5] = their number,
+    // [8d+6], [8d+7] = arena state before the kept list was taken.
+    uint32_t d = 2;
+    const uint32_t *C = cid + i + 1;
+    uint32_t nc = k - i - 1;
+    bool fresh = true;
+    uint32_t *K = nullptr;
+    uint32_t nk = 0, t = 0;
+    for (;;) {
+        if (fresh) {
+            fresh = false;
+            if (past_deadline(jb.deadline)) {
+                *timed_out = true;
+                return;
+            }
+            if (d + 1 == pA) {
+                // leaves: every candidate c of this node adds C(|S n N(c)|, q)
+                if (HYBRID) {
+                    for (uint32_t b0 = 0; b0 < nc; b0 += kWaveSize) {
+                        const uint32_t b = b0 + ln;
+                        if (b < nc) {
+                            const uint32_t n = set_count<MODE>(jb, S, m, C[b]);
+                            if (n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
+                        }
+                    }
+                } else {
+                    for (uint32_t b = 0; b < nc; ++b) {
+                        const uint32_t n = set_count_wave<MODE>(jb, S, m, C[b]);
+                        if (ln == 0 && n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
+                    }
+                }
+                if (instrument) ct.filter_words += (unsigned long long)nc * m;
+                goto pop;
+            }
+            // keep the candidates that leave at least q common neighbours
+            stk[8 * d + 6] = ar.lds_used;
+            stk[8 * d + 7] = ar.slab_used;
+            K = (uint32_t *)arena_alloc(ar, (nc + 1) / 2 + 1, cap_fail);
+            if (!K) return;
+            nk = 0;
+            if (HYBRID) {
+                for (uint32_t b0 = 0; b0 < nc; b0 += kWaveSize) {
+                    const uint32_t b = b0 + ln;
+                    const bool valid = b < nc;
+                    const uint32_t c = valid ? C[b] : 0u;
+                    const bool keep = valid && set_count<MODE>(jb, S, m, c) >= q;
+                    const uint64_t mask = __ballot(keep);
+                    if (keep) K[nk + mbcnt64(mask)] = c;
+                    nk += (uint32_t)__popcll(mask);
+                }
+            } else {
+                for (uint32_t b = 0; b < nc; ++b) {
+                    const uint32_t c = C[b];
+                    if (set_count_wave<MODE>(jb, S, m, c) >= q) {
+                        if (ln == 0) K[nk] = c;
+                        ++nk;
+                    }
+                }
+            }
+            wave_sync();
+            if (instrument) ct.filter_words += (unsigned long long)nc * m;
+            t = 0;
+        }
+        // next child {.., K[t]}: it needs pA - d vertices from K[t ..]
+        if (nk - t < pA - d) goto pop;
+        {
+            const uint32_t a = K[t++];
+            // save this level, then build the child's set
+            stk[8 * d + 0] = (uint64_t)(uintptr_t)S;
+            stk[8 * d + 1] = m;
+            stk[8 * d + 2] = (uint64_t)(uintptr_t)K;
+            stk[8 * d + 3] = ((uint64_t)t << 32) | nk;
+            stk[8 * d + 4] = (uint64_t)(uintptr_t)C;
+            stk[8 * d + 5] = nc;
+            wave_sync();
+            uint64_t *S2 = arena_alloc(ar, m, cap_fail);
+            if (!S2) return;
+            uint32_t nb = 0;
+            const uint32_t m2 = set_intersect<MODE>(jb, S, m, false, 0, a, S2, &nb);
+            if (instrument) ct.filter_words += m;
+            S = S2;
+            m = m2;
+            C = K + t;
+            nc = nk - t;
+            ++d;
+            fresh = true;
+            continue;
+        }
+    pop:
+        if (d == 2) return;
+        --d;
+        // release the child's allocations (its set and kept list): back to
+        // the marks taken before this level's kept list, plus that list
+        {
+            S = (uint64_t *)(uintptr_t)stk[8 * d + 0];
+            m = (uint32_t)stk[8 * d + 1];
+            K = (uint32_t *)(uintptr_t)stk[8 * d + 2];
+            t = (uint32_t)(stk[8 * d + 3] >> 32);
+            nk = (uint32_t)stk[8 * d + 3];
+            C = (const uint32_t *)(uintptr_t)stk[8 * d + 4];
+            nc = (uint32_t)stk[8 * d + 5];
+            const uint32_t kw = (nc + 1) / 2 + 1;
+            ar.lds_used = (uint32_t)stk[8 * d + 6];
+            ar.slab_used = stk[8 * d + 7];
+            // re-take the kept list's words at the same place (it is still there)
+            bool f = false;
+            uint32_t *K2 = (uint32_t *)arena_alloc(ar, kw, &f);
+            if (K2 != K) {   // cannot happen: the same request from the same state
+                *cap_fail = true;
+                return;
+            }
+        }
+    }
+}
+
+template <uint32_t MODE, bool HYBRID>
+__global__ __launch_bounds__(kBlockThreads) void k_enumerate_sets(SetParams prm)
+{
+    __shared__ uint64_t lds[kWavesPerBlock][kSetLdsWords];
+    __shared__ uint64_t stk[kWavesPerBlock][8 * kSetLevels];
+    const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
+    const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    Arena arena;
+    arena.lds = &lds[wv][0];
+    arena.lds_cap = kSetLdsWords;
+    arena.lds_used = 0;
+    arena.slab = prm.slab + wave_global * prm.slab_words;
+    arena.slab_cap = prm.slab_words;
+    arena.slab_used = 0;
+    const bool instrument = prm.instrument != 0;
+    Acc acc;
+    acc.v = 0;
+    acc.ovf = false;
+    acc.t = 0;
+    Counters ct{};
+    uint32_t cur_job = 0xffffffffu;
+    for (;;) {
+        unsigned long long t0 = 0;
+        if (ln == 0) t0 = atomicAdd(prm.queue, (unsigned long long)prm.task_chunk);
+        t0 = bcast64(t0, 0);
+        if (t0 >= prm.n_tasks) break;
+        const unsigned long long t_end = min(t0 + prm.task_chunk, (unsigned long long)prm.n_tasks);
+        uint32_t r = 0, hi = prm.n_roots;
+        while (hi - r > 1) {
+            const uint32_t mid = (r + hi) >> 1;
+            if (prm.roots[mid].task_begin <= t0) r = mid;
+            else hi = mid;
+        }
+        SetRoot rt = prm.roots[r];
+        for (unsigned long long t = t0; t < t_end; ++t) {
+            while (t >= rt.task_begin + rt.n_tasks) rt = prm.roots[++r];   // every root owns >= 1 task
+            if (rt.job != cur_job) {
+                if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
+                cur_job = rt.job;
+            }
+            const Job jb = prm.jobs[rt.job];
+            bool cap_fail = false, timed_out = past_deadline(jb.deadline);
+            if (!timed_out)
+                run_set_task<MODE, HYBRID>(jb, rt, (uint32_t)(t - rt.task_begin), prm.ids, arena, &stk[wv][0], acc,
+                                           ct, instrument, &cap_fail, &timed_out);
+            if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
+            if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
+        }
+    }
+    if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
+}
+
+hipError_t launch_enumerate_sets(const SetParams &prm, uint32_t n_blocks, hipStream_t stream)
+{
+    if (prm.n_tasks == 0) return hipSuccess;
+    const bool hybrid = prm.pure_dfs == 0;
+    if (prm.mode == SETS_HTB && hybrid)
+        hipLaunchKernelGGL((k_enumerate_sets<SETS_HTB, true>), dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
+    else if (prm.mode == SETS_HTB)
+        hipLaunchKernelGGL((k_enumerate_sets<SETS_HTB, false>), dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
+    else if (hybrid)
+        hipLaunchKernelGGL((k_enumerate_sets<SETS_SORTED, true>), dim3(n_blocks), dim3(kBlockThreads), 0, stream,
+                           prm);
+    else
+        hipLaunchKernelGGL((k_enumerate_sets<SETS_SORTED, false>), dim3(n_blocks), dim3(kBlockThreads), 0, stream,
+                           prm);
     return hipGetLastError();
 }
 

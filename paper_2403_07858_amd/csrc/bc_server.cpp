@@ -1,8 +1,10 @@
 // Counting service over device-resident graphs: memory-admitted continuous
-// batching (include/bc_server.h).  Worker threads each own a HIP stream and
-// run one batch at a time through the batched device path; several workers
-// keep several batches in flight, so new queries join the device while
-// earlier ones are still running.
+// batching (include/bc_server.h).  Worker threads each own a stream and run
+// one batch at a time through the batched device path; several workers keep
+// several batches in flight, so new queries join the device while earlier
+// ones are still running.  This file is the scheduler only: every device
+// call goes through a bcint::ServerBackend (bc_server_hip.cpp for the HIP
+// one), so the scheduler builds and runs on a host without a GPU too.
 #include "bc_server.h"
 
 #include <algorithm>
@@ -15,8 +17,6 @@
 #include <thread>
 #include <unordered_map>
 #include <vector>
-
-#include <hip/hip_runtime.h>
 
 #include "bc_internal.h"
 
@@ -38,6 +38,7 @@ struct Ticket {
 
 struct bc_server {
     bc_server_opts opts{};
+    const bcint::ServerBackend *be = nullptr;
     std::vector<const bc_graph *> graphs;
     std::mutex mu;
     std::condition_variable cv_work;   // pending queue or budget changed
@@ -49,6 +50,8 @@ struct bc_server {
     uint64_t inflight_bytes = 0;
     uint32_t inflight_batches = 0;
     bool stop = false;
+    uint32_t pollers = 0;              // threads inside bc_server_poll (destroy waits for them)
+    uint64_t last_deadline_scan = 0;   // steady ns of the last scan of the pending queue for expired deadlines
     std::vector<std::thread> workers;
     // statistics
     uint64_t submitted = 0, completed = 0, rejected = 0, timed_out = 0, failed = 0, batches = 0, batched_queries = 0;
@@ -58,6 +61,11 @@ struct bc_server {
 };
 
 namespace {
+
+// Wave slots per CU of one worker's batches: the enumeration grid is
+// persistent, so at full size one batch would hold every CU until it ends
+// and the other workers' batches could not start; each takes its share.
+uint32_t worker_waves(const bc_server *s) { return std::max(1u, 12u / std::max(1u, s->opts.max_inflight)); }
 
 void finish(bc_server *s, Ticket &t, bc_status st, bc_u128 v, uint64_t now)
 {
@@ -70,6 +78,8 @@ void finish(bc_server *s, Ticket &t, bc_status st, bc_u128 v, uint64_t now)
         s->latencies_ms.push_back((double)(now - t.t_submit) / 1e6);
     } else if (st == BC_E_TIMEOUT) {
         s->timed_out++;
+    } else if (st == BC_E_REJECTED) {
+        s->rejected++;   // refused by the cost model after admission
     } else if (st != BC_E_CANCELLED) {
         s->failed++;
     }
@@ -77,13 +87,13 @@ void finish(bc_server *s, Ticket &t, bc_status st, bc_u128 v, uint64_t now)
 
 void worker_main(bc_server *s)
 {
-    hipStream_t stream = nullptr;
+    int device = 0;
     {
         // graphs may still be being added (the vector can reallocate)
         std::lock_guard<std::mutex> lk(s->mu);
-        if (!s->graphs.empty()) (void)hipSetDevice(bcint::graph_device(s->graphs[0]));
+        if (!s->graphs.empty()) device = s->be->device(s->graphs[0]);
     }
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    void *stream = s->be->stream_create(device);
     const uint32_t max_batch = s->opts.max_batch ? s->opts.max_batch : 256;
     for (;;) {
         std::vector<uint64_t> batch;
@@ -92,9 +102,12 @@ void worker_main(bc_server *s)
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
                 if (s->stop) break;
-                // drop queries whose deadline passed while they waited
+                // drop queries whose deadline passed while they waited (a scan
+                // of the whole queue under the lock: at most once a millisecond)
                 const uint64_t now = bcint::steady_ns();
-                for (auto it = s->pending.begin(); it != s->pending.end();) {
+                const bool scan = now - s->last_deadline_scan >= 1000000ull;
+                if (scan) s->last_deadline_scan = now;
+                for (auto it = s->pending.begin(); scan && it != s->pending.end();) {
                     Ticket &t = s->tickets[*it];
                     if (t.deadline_ns && now >= t.deadline_ns) {
                         finish(s, t, BC_E_TIMEOUT, bc_u128{0, 0}, now);
@@ -155,11 +168,10 @@ void worker_main(bc_server *s)
         o.struct_size = sizeof(bc_opts);
         o.stream = stream;
         o.anchor = BC_ANCHOR_AUTO;
-        // the enumeration grid is persistent: at full size one batch would
-        // hold every CU until it ends, and the batches of the other workers
-        // could not start; each worker takes its share of the wave slots
-        o.waves_per_cu = std::max(1u, 12u / std::max(1u, s->opts.max_inflight));
-        bc_status rc = bcint::count_queries(qs.data(), qs.size(), &o, out.data(), st.data());
+        o.waves_per_cu = worker_waves(s);
+        // the batch may take what admission charged for it, no more
+        o.scratch_cap_bytes = batch_bytes;
+        s->be->count(qs.data(), qs.size(), &o, out.data(), st.data());
         {
             std::lock_guard<std::mutex> lk(s->mu);
             const uint64_t now = bcint::steady_ns();
@@ -167,7 +179,7 @@ void worker_main(bc_server *s)
                 Ticket &t = s->tickets[batch[i]];
                 t.batch_id = batch_id;
                 t.batch_size = (uint32_t)batch.size();
-                finish(s, t, (rc == BC_OK || rc == BC_E_DEVICE) ? st[i] : rc, out[i], now);
+                finish(s, t, st[i], out[i], now);   // st[i] is the call's status unless counts were read
             }
             s->inflight_bytes -= batch_bytes;
             s->inflight_batches--;
@@ -175,32 +187,23 @@ void worker_main(bc_server *s)
         s->cv_done.notify_all();
         s->cv_work.notify_all();
     }
-    if (stream) (void)hipStreamDestroy(stream);
+    if (stream) s->be->stream_destroy(stream);
 }
 
 }  // namespace
 
-extern "C" bc_status bc_server_create(const bc_server_opts *opts, bc_server **out)
+bc_status bcint::server_create(const bc_server_opts *opts, const ServerBackend *backend, bc_server **out)
 {
-    if (!out) return BC_E_INVALID_ARG;
+    if (!out || !backend) return BC_E_INVALID_ARG;
     bc_server *s = new (std::nothrow) bc_server();
     if (!s) return BC_E_OOM;
+    s->be = backend;
     if (opts) s->opts = *opts;
     if (!s->opts.max_inflight) s->opts.max_inflight = 2;
     if (s->opts.max_inflight > 16) s->opts.max_inflight = 16;
     if (!s->opts.max_batch) s->opts.max_batch = 256;
     if (!s->opts.max_pending) s->opts.max_pending = 65536;
-    if (!s->opts.memory_budget_bytes) {
-        // memory cached by earlier counts is not in use: give it back first
-        int dev = 0;
-        hipMemPool_t pool;
-        if (hipGetDevice(&dev) == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
-            hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
-            (void)hipMemPoolTrimTo(pool, 0);
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) free_b = 8ull << 30;
-        s->opts.memory_budget_bytes = free_b / 2;
-    }
+    if (!s->opts.memory_budget_bytes) s->opts.memory_budget_bytes = backend->default_budget();
     s->t_created = bcint::steady_ns();
     *out = s;
     return BC_OK;
@@ -210,7 +213,7 @@ extern "C" bc_status bc_server_add_graph(bc_server *s, const bc_graph *g, uint32
 {
     if (!s || !g || !graph_id) return BC_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (!s->graphs.empty() && bcint::graph_device(g) != bcint::graph_device(s->graphs[0])) return BC_E_INVALID_ARG;
+    if (!s->graphs.empty() && s->be->device(g) != s->be->device(s->graphs[0])) return BC_E_INVALID_ARG;
     *graph_id = (uint32_t)s->graphs.size();
     s->graphs.push_back(g);
     // workers start with the first graph (they bind to its device)
@@ -232,7 +235,7 @@ extern "C" bc_status bc_server_submit(bc_server *s, uint32_t graph_id, uint32_t 
     t.p = p;
     t.q = q;
     t.deadline_ns = deadline_ns;
-    t.est_bytes = bcint::estimate_scratch_bytes(s->graphs[graph_id], p, q);
+    t.est_bytes = s->be->estimate(s->graphs[graph_id], p, q, worker_waves(s));
     t.t_submit = bcint::steady_ns();
     t.done = false;
     if (t.est_bytes > s->opts.memory_budget_bytes || s->pending.size() >= s->opts.max_pending) {
@@ -255,10 +258,15 @@ extern "C" bc_status bc_server_poll(bc_server *s, uint64_t ticket, int block, bc
     if (it == s->tickets.end()) return BC_E_NOT_FOUND;
     if (!it->second.done) {
         if (!block) return BC_E_PENDING;
+        // counted while waiting, so that bc_server_destroy does not free the
+        // server under a poll that is about to wake up
+        s->pollers++;
         s->cv_done.wait(lk, [&] {
             auto jt = s->tickets.find(ticket);
             return jt == s->tickets.end() || jt->second.done;
         });
+        s->pollers--;
+        if (s->pollers == 0) s->cv_done.notify_all();
         it = s->tickets.find(ticket);
         if (it == s->tickets.end()) return BC_E_NOT_FOUND;
     }
@@ -322,5 +330,10 @@ extern "C" void bc_server_destroy(bc_server *s)
     s->cv_work.notify_all();
     s->cv_done.notify_all();
     for (auto &w : s->workers) w.join();
+    {
+        // every query is final now; wait until the pollers woken by it have left
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] { return s->pollers == 0; });
+    }
     delete s;
 }

@@ -191,6 +191,49 @@ def test_batch_matches_single(bc):
     assert st2 == st and vals2 == vals
 
 
+def _oracle_total(g, p, q, max_nodes=2_000_000):
+    """Whole count from per-root oracle counts under a per-root budget, on
+    the side whose tree is shallower first; None if neither side finishes."""
+    for a in (("U", "V") if p <= q else ("V", "U")):
+        n = g.n_u if a == "U" else g.n_v
+        per = oracle.count_ranks(g, p, q, list(range(n)), anchor=a, order_key=oracle.ORDER_DEGREE,
+                                 max_nodes=max_nodes)
+        if all(x is not None for x in per):
+            return sum(per)
+    return None
+
+
+def test_batch_c4_items_unclamped(bc):
+    # 80 items of the 4096-graph batch workload with |U| <= 1000, each with
+    # its own (p,q) drawn from {2..6}^2, in one batched call; every count
+    # against the oracle (items whose oracle run exceeds its budget on both
+    # sides are left out and counted)
+    idx = _small_batch_indices(80, max_u=1000)
+    raw, graphs, ps, qs = [], [], [], []
+    for i in idx:
+        g, p, q = gg.batch_graph(i)
+        raw.append(g)
+        graphs.append(bc.build_graph(g))
+        ps.append(p)
+        qs.append(q)
+    assert len({(p, q) for p, q in zip(ps, qs)}) >= 15
+    assert max(ps) == 6 and max(qs) == 6
+    vals, st = bc.bc_count_batch(graphs, ps, qs)
+    assert all(s == bc.BC_OK for s in st)
+    compared = 0
+    for i, g in enumerate(raw):
+        want = _oracle_total(g, ps[i], qs[i])
+        say("c4 item", idx[i], (ps[i], qs[i]), g.n_u, g.n_edges, vals[i], want)
+        if want is None:
+            continue
+        assert vals[i] == want, (idx[i], ps[i], qs[i])
+        compared += 1
+    assert compared >= 76
+    # the same items one call each
+    for i in range(0, len(raw), 5):
+        assert bc.bc_count(graphs[i], ps[i], qs[i]) == vals[i]
+
+
 # ---------------------------------------------------------------------------
 # Full-size power-law graph (2M edges): sampled and property checks.
 

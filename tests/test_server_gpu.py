@@ -6,6 +6,7 @@ import time
 
 import pytest
 
+import oracle
 from paper_2403_07858_amd import graphgen as gg
 
 pytestmark = pytest.mark.gpu
@@ -41,6 +42,8 @@ def test_alone_and_in_mix_are_identical(bc, graphs):
     for gid, p, q in qs:
         if (gid, p, q) not in solo:
             solo[(gid, p, q)] = bc.bc_count(G[gid], p, q)
+            # the served results below are compared with these, which equal the oracle
+            assert solo[(gid, p, q)] == oracle.count(raw[gid], p, q), (gid, p, q)
     srv = bc.Server(max_inflight=3, max_batch=8)
     ids = [srv.add_graph(g) for g in G]
     assert ids == [0, 1, 2, 3]
@@ -111,3 +114,47 @@ def test_device_time_limit(bc):
     assert time.time() - t0 < 30
     # the library keeps working afterwards
     assert bc.bc_count(G, 1, 1) == g.n_edges
+
+
+def test_scratch_estimate_bounds_a_capped_count(bc, graphs):
+    # the admission estimate is an upper bound on what a count capped at it
+    # takes (the server caps each batch at the sum of its estimates), and the
+    # capped count is the oracle's
+    raw, G = graphs
+    for gid, p, q in ((0, 3, 3), (1, 4, 4), (2, 5, 3), (3, 5, 5), (1, 2, 6)):
+        for waves in (12, 4):
+            est = bc.bc_scratch_estimate(G[gid], p, q, waves_per_cu=waves)
+            got, st = bc.bc_count(G[gid], p, q, waves_per_cu=waves, scratch_cap_bytes=est, with_stats=True)
+            say("estimate", gid, (p, q), waves, est, "taken", st["scratch_bytes"])
+            assert 0 < st["scratch_bytes"] <= est
+            assert got == oracle.count(raw[gid], p, q)
+    # a cap too small for anything fails cleanly
+    with pytest.raises(bc.BCError) as e:
+        bc.bc_count(G[1], 4, 4, scratch_cap_bytes=4096)
+    assert e.value.status == bc.BC_E_OOM
+    assert bc.bc_count(G[1], 4, 4) == oracle.count(raw[1], 4, 4)
+
+
+def test_cost_model_refuses_what_cannot_meet_its_deadline(bc, graphs):
+    # once a served batch has timed one job of a depth, a job of that depth
+    # whose planning proxy puts it far past its deadline is refused before
+    # its enumeration (BC_E_REJECTED) instead of running until it expires
+    raw, G = graphs
+    big = bc.build_graph(gg.power_law_2m())
+    srv = bc.Server(max_inflight=1, max_batch=1)
+    small = srv.add_graph(G[0])
+    heavy = srv.add_graph(big)
+    t = srv.submit(small, 5, 5)
+    st, val, _ = srv.poll(t)
+    assert st == bc.BC_OK and val == oracle.count(raw[0], 5, 5)
+    t = srv.submit(heavy, 5, 5, deadline_ns=srv.now_ns() + 50_000_000)   # (5,5) on 2M edges takes seconds
+    st, val, info = srv.poll(t)
+    s = srv.stats()
+    say("heavy (5,5) with a 50 ms deadline:", bc.bc_status_string(st), info, s)
+    assert st in (bc.BC_E_REJECTED, bc.BC_E_TIMEOUT) and val is None
+    assert s["rejected"] + s["timed_out"] == 1
+    # and what fits still runs
+    t = srv.submit(small, 4, 4, deadline_ns=srv.now_ns() + 30_000_000_000)
+    st, val, _ = srv.poll(t)
+    assert st == bc.BC_OK and val == oracle.count(raw[0], 4, 4)
+    srv.close()
