@@ -147,7 +147,23 @@ def main():
             f"cycle share " + " ".join(f"{k[4:]}={v / tot:.2f}" for k, v in cyc.items()) +
             f" pack={st['cyc_pack'] / tot:.2f} task_cycles={tot:.4g}"
             f" pairs={st['pairs']} lane_use={st['pairs'] / max(1, st['pair_slots']):.2f} "
-            f"words/pair={st['pair_ops'] / max(1, st['pairs']):.2f}")
+            f"words/pair={st['pair_ops'] / max(1, st['pairs']):.2f} wave makespan={st['ms_wave_makespan']:.1f}ms "
+            f"spread={st['ms_wave_spread']:.1f}ms")
+
+    # load balance of the deep queries: per-wave makespan and spread with the
+    # runtime split off (the default) and on (heavy tasks queue their level-3 nodes)
+    balance = []
+    for p, q in queries:
+        if min(p, q) < 5:
+            continue
+        for rows in (0xFFFFFFFF, 256):
+            c, st = bc.bc_count(G, p, q, with_stats=True, instrument=True, stream=stream, split_rows=rows)
+            assert c == algo[(p, q)][0]
+            balance.append({"p": p, "q": q, "split_rows": None if rows == 0xFFFFFFFF else rows,
+                            "ms_enumerate": st["ms_enumerate"], "wave_makespan_ms": st["ms_wave_makespan"],
+                            "wave_spread_ms": st["ms_wave_spread"]})
+            log(f"[bench] ({p},{q}) split_rows={balance[-1]['split_rows']}: enum {st['ms_enumerate']:.1f} ms, "
+                f"wave makespan {st['ms_wave_makespan']:.1f} ms, spread {st['ms_wave_spread']:.1f} ms")
 
     def step():
         out = []
@@ -203,6 +219,7 @@ def main():
                           "bicliques_per_s": c / (mt / 1000), "root_vertices_per_s": st["roots"] / (mt / 1000),
                           "anchor": "UV"[st["anchor"]], "tasks": st["tasks"],
                           "word_intersections": w,
+                          "wave_makespan_ms": st["ms_wave_makespan"], "wave_spread_ms": st["ms_wave_spread"],
                           "lds_frac": (BYTES_PER_WORD * w / (ms / 1000)) / peaks["lds_bytes_per_s"] if ms > 0 else 0.0,
                           "leaf_pairs_per_s": st["pairs"] / (ms / 1000) if ms > 0 else 0.0})
 
@@ -250,6 +267,7 @@ def main():
                                          "note": "leaf pair sums as the int8 product of bit-expanded rows"}},
         "cpu_baseline": cpu,
         "capped_sweep": sweep,
+        "load_balance": balance,
         "batched_vs_per_query_speedup": batch["batched_vs_per_query_speedup"] if batch else None,
         "batch": batch,
     }
@@ -430,6 +448,18 @@ def batch_measure(n, steps, timeout_ms, log):
     t_single = time.perf_counter() - t0
     log(f"[batch] one launch set per graph: {t_single * 1e3:.1f} ms; default schedule batched: "
         f"{t_default * 1e3:.1f} ms")
+    # load balance of the batched launch: per-wave makespan and spread with the
+    # runtime split off and on (instrumented passes, counts compared)
+    balance = []
+    for rows in (0xFFFFFFFF, 256):
+        o2 = dict(opt)
+        o2["split_rows"] = rows
+        v2, s2, a2 = bc.bc_count_batch(graphs, ps, qs, with_stats=True, instrument=True, **o2)
+        balance.append({"split_rows": None if rows == 0xFFFFFFFF else rows, "ms_enumerate": a2["ms_enumerate"],
+                        "wave_makespan_ms": a2["ms_wave_makespan"], "wave_spread_ms": a2["ms_wave_spread"],
+                        "same_counts": v2 == vals and s2 == st})
+        log(f"[batch] split_rows={balance[-1]['split_rows']}: enum {a2['ms_enumerate']:.1f} ms, wave makespan "
+            f"{a2['ms_wave_makespan']:.1f} ms, spread {a2['ms_wave_spread']:.1f} ms")
     mismatch = sum(1 for a, b, s, s2 in zip(vals, single_vals, st, single_st)
                    if s == bc.BC_OK and s2 == bc.BC_OK and a != b)
     mismatch += sum(1 for a, b, s, s2 in zip(vals, vals_d, st, st_d) if s == bc.BC_OK and s2 == bc.BC_OK and a != b)
@@ -439,7 +469,7 @@ def batch_measure(n, steps, timeout_ms, log):
             "ms_batched": t_batch * 1e3, "ms_per_query_launches": t_single * 1e3,
             "batched_vs_per_query_speedup": t_single / t_batch,
             "ms_batched_default_schedule": t_default * 1e3, "autotuner_gain": t_default / t_batch,
-            "schedule": tuned, "autotune_ms": t_tune * 1e3,
+            "schedule": tuned, "autotune_ms": t_tune * 1e3, "load_balance": balance,
             "completed": sum(1 for s in st if s == bc.BC_OK),
             "statuses": {bc.bc_status_string(s): st.count(s) for s in set(st)},
             "mismatches": mismatch}

@@ -166,6 +166,9 @@ typedef struct {
     uint64_t cyc_pack;         /* instrumented: the part of cyc_compact spent in tasks whose common
                                   neighbourhood had to be bit-packed (spread over more words than it needs) */
     uint64_t scratch_bytes;    /* device scratch the call took (all of it held until the call ends) */
+    double ms_wave_makespan;   /* instrumented: first wavefront start to last wavefront end of the
+                                  local-bitmap enumeration (device real-time clock) */
+    double ms_wave_spread;     /* instrumented: first to last wavefront end (load imbalance) */
 } bc_stats;
 
 /*
@@ -248,6 +251,36 @@ bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, int32_t anch
  */
 bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q,
                          size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st);
+
+/*
+ * bc_partition -- BCPar (Algorithm 3, Section VI): groups the roots of one
+ * anchor side (BC_ANCHOR_U or _V; the anchor's depth, p for U and q for V,
+ * must be at least 3) so that each group's closure -- its roots, their
+ * oriented 2-hop candidates (ranked after the root, sharing at least q
+ * neighbours for anchor U, p for V) and the neighbourhoods of all of them --
+ * takes at most budget_bytes, counting 4 bytes per adjacency entry and per
+ * candidate entry of each member (w(u) = |N(u)| + |N_2(u)|).  Greedy: a
+ * group starts from the unassigned root of highest average candidate
+ * weight and keeps taking the unassigned root that shares the most weight
+ * with its closure while the budget holds (a root whose closure alone is
+ * over budget forms a group by itself).  part_of_rank[r] (one entry per
+ * vertex of the side) receives the group of the root of rank r; *n_parts
+ * the number of groups.  Candidate sets are computed on the host.
+ */
+bc_status bc_partition(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor, uint64_t budget_bytes,
+                       uint32_t *part_of_rank, uint32_t *n_parts);
+
+/*
+ * bc_count_partition -- the part of the count whose lowest-ranked L vertex
+ * is a root of group `part` (part_of_rank as from bc_partition), computed on
+ * the group's closure alone: that subgraph is built, uploaded, counted with
+ * only the group's roots owning tasks, and freed.  Over all groups these
+ * counts add up to bc_count.  *closure_edges (nullable) receives the
+ * closure's edge count.  Same argument rules as bc_partition.
+ */
+bc_status bc_count_partition(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor,
+                             const uint32_t *part_of_rank, uint32_t part, const bc_opts *opts, bc_u128 *out,
+                             uint64_t *closure_edges);
 
 /*
  * bc_scratch_estimate -- an upper bound on the device scratch of bc_count(g,

@@ -124,7 +124,8 @@ class bc_stats(ctypes.Structure):
                 ("pair_ops", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64),
                 ("cyc_setup", ctypes.c_uint64), ("cyc_compact", ctypes.c_uint64), ("cyc_pair", ctypes.c_uint64),
                 ("cyc_filter", ctypes.c_uint64), ("pairs", ctypes.c_uint64), ("pair_slots", ctypes.c_uint64),
-                ("cyc_pack", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64)]
+                ("cyc_pack", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
+                ("ms_wave_makespan", ctypes.c_double), ("ms_wave_spread", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -149,6 +150,8 @@ def _load():
         "bc_count_batch": ([P, P, P, SZ, P, P, P, P], I32),
         "bc_tune_batch": ([P, P, P, SZ, P, P], I32),
         "bc_scratch_estimate": ([P, U32, U32, P, P], I32),
+        "bc_partition": ([P, U32, U32, I32, U64, P, P], I32),
+        "bc_count_partition": ([P, U32, U32, I32, P, U32, P, P, P], I32),
         "bc_status_string": ([I32], ctypes.c_char_p),
         "bc_last_error": ([], ctypes.c_char_p),
     }
@@ -162,7 +165,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_htb_stats", "bc_count", "bc_count_roots", "bc_count_batch",
-            "bc_tune_batch", "bc_scratch_estimate", "bc_status_string", "bc_last_error")
+            "bc_tune_batch", "bc_scratch_estimate", "bc_partition", "bc_count_partition", "bc_status_string", "bc_last_error")
 
 
 class BCError(RuntimeError):
@@ -346,6 +349,29 @@ def bc_scratch_estimate(g: Graph, p: int, q: int, **opt) -> int:
     if s != BC_OK:
         raise BCError(s, "bc_scratch_estimate")
     return b.value
+
+
+def bc_partition(g: Graph, p: int, q: int, anchor: int, budget_bytes: int):
+    """(part_of_rank array, number of groups) of BCPar over the anchor side's roots."""
+    n = g.n_u if anchor == BC_ANCHOR_U else g.n_v
+    part = np.zeros(max(1, n), dtype=np.uint32)
+    npart = ctypes.c_uint32()
+    s = _lib.bc_partition(g.handle, p, q, anchor, budget_bytes, part.ctypes.data, ctypes.byref(npart))
+    if s != BC_OK:
+        raise BCError(s, "bc_partition")
+    return part[:n], npart.value
+
+
+def bc_count_partition(g: Graph, p: int, q: int, anchor: int, part_of_rank, part: int, **opt):
+    """(count of group `part`, edges of its closure subgraph)."""
+    pr = np.ascontiguousarray(part_of_rank, dtype=np.uint32)
+    o = make_opts(**opt)
+    out, edges = bc_u128(), ctypes.c_uint64()
+    s = _lib.bc_count_partition(g.handle, p, q, anchor, pr.ctypes.data, part, ctypes.byref(o), ctypes.byref(out),
+                                ctypes.byref(edges))
+    if s != BC_OK:
+        raise BCError(s, "bc_count_partition")
+    return out.value, edges.value
 
 
 def bc_tune_batch(graphs, ps, qs, **opt) -> dict:

@@ -129,8 +129,11 @@ struct EnumParams {
     uint32_t split_rows;    // level-2 blocks with more rows are split into queued subtasks
     uint32_t split_cap;     // subtask ring entries (0 = no splitting)
     uint4 *ring;            // subtask ring, split_cap entries, all zero at launch
-    unsigned long long *sub_head;   // subtask entries claimed (zero at launch)
+    unsigned long long *sub_head;   // [0] subtask entries claimed, [2] split heap words taken (zero at launch)
     unsigned long long *sub_tail;   // subtask entries reserved (zero at launch)
+    uint64_t *split_heap;   // level-2 blocks of split tasks
+    uint64_t split_heap_words;
+    unsigned long long *wave_clock; // instrumented: per wavefront {first task start, end} device clock ticks
     unsigned long long *queue;   // task counter: tasks popped in the low 40 bits; with splitting on,
                                  // wavefronts still running a popped chunk in the bits above
     Slot *slots;

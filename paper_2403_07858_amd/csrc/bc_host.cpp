@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <queue>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -222,8 +223,7 @@ std::vector<uint32_t> border_order(uint64_t n, const std::vector<uint32_t> &orde
     for (uint64_t x = 0; x < n; ++x)
         for (uint64_t e = ptr_x[x]; e < ptr_x[x + 1]; ++e) ones[x] += cnt[cols_x[e]][pos[x] >> 5] == 1;
     std::vector<char> stuck(n, 0);     // no profitable swap found for it
-    std::vector<uint32_t> overlap(n, 0);
-    std::vector<uint32_t> touched;
+    std::vector<uint8_t> overlap(n_rows, 0);   // per row: holds a (1), both a and b (2)
     // the single member of block b of row r (the block must hold exactly one)
     auto alone = [&](uint32_t r, uint32_t b) -> uint32_t {
         for (uint64_t e = ptr_o[r]; e < ptr_o[r + 1]; ++e)
@@ -255,7 +255,6 @@ std::vector<uint32_t> border_order(uint64_t n, const std::vector<uint32_t> &orde
         }
         return -delta;
     };
-    (void)touched;
     for (uint64_t it = 0; it < iters; ++it) {
         // Step 1: the vertex in the most 1-blocks
         uint32_t vm = 0xffffffffu;
@@ -304,7 +303,10 @@ std::vector<uint32_t> border_order(uint64_t n, const std::vector<uint32_t> &orde
         hit.erase(std::unique(hit.begin(), hit.end()), hit.end());
         for (const auto &h : hit) {   // old singles lose their 1-block
             auto f = cnt[h.first].find(h.second);
-            if (f != cnt[h.first].end() && f->second == 1) ones[alone(h.first, h.second)]--;
+            if (f != cnt[h.first].end() && f->second == 1) {
+                const uint32_t x = alone(h.first, h.second);
+                if (x != 0xffffffffu) ones[x]--;
+            }
         }
         for (uint64_t e = ptr_x[vm]; e < ptr_x[vm + 1]; ++e) {
             auto &m = cnt[cols_x[e]];
@@ -320,7 +322,10 @@ std::vector<uint32_t> border_order(uint64_t n, const std::vector<uint32_t> &orde
         std::swap(pos[vm], pos[vn]);
         for (const auto &h : hit) {   // new singles gain one
             auto f = cnt[h.first].find(h.second);
-            if (f != cnt[h.first].end() && f->second == 1) ones[alone(h.first, h.second)]++;
+            if (f != cnt[h.first].end() && f->second == 1) {
+                const uint32_t x = alone(h.first, h.second);
+                if (x != 0xffffffffu) ones[x]++;
+            }
         }
         stuck[vn] = 0;
     }
@@ -726,6 +731,7 @@ struct JobSpec {
     uint64_t rank_lo, rank_hi; // only used when ranged
     bool ranged;
     uint64_t deadline_ns;      // steady clock, 0 = none
+    const std::vector<uint8_t> *root_mask = nullptr;   // p_A >= 3 only: roots (by rank) that get tasks
 };
 
 // Device real-time clock against the host steady clock, per device.  The
@@ -1351,10 +1357,12 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         if (!job_live[j]) continue;
         const HostJob &hj = jobs[j];
         const Side &A = specs[hj.spec].g->side[hj.anchor];
+        const std::vector<uint8_t> *mask = specs[hj.spec].root_mask;
         for (uint64_t r = root_prefix[c]; r < root_prefix[c + 1]; ++r) {
             cand_edges += h_k[r];
             if (hj.pA < 3 || h_k[r] < hj.pA - 1) continue;
             uint32_t u = (uint32_t)(hj.root_lo + (r - root_prefix[c]));
+            if (mask && !(*mask)[u]) continue;
             uint32_t w1 = (uint32_t)((A.h_ptr[u + 1] - A.h_ptr[u] + 63) / 64);
             uint64_t k = h_k[r];
             uint64_t x = k * w1;
@@ -1466,6 +1474,8 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
 
     tm.mark(2, st);
     const uint64_t t_enum0 = bcint::steady_ns();
+    unsigned long long *d_wave_clock = nullptr;   // instrumented: per-wave start / end clocks
+    uint64_t n_wave_clock = 0;
     if (!plan.empty()) {
         bcdev::ActiveRoot *d_roots;
         uint64_t *d_pool = d_pool_fused;
@@ -1478,22 +1488,29 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
                                             d_queue + 1, d_slots, st));
         }
         tm.mark(3, st);
-        // Subtask ring of the runtime split (queries with p_A >= 5): up to 4M
-        // entries of 16 bytes, cleared before the launch.
+        // Runtime split (queries with p_A >= 5): a subtask ring of up to 4M
+        // entries of 16 bytes, cleared before the launch, and a heap of up to
+        // 64M words for the split tasks' level-2 blocks.
         uint32_t split_cap = 0;
         uint4 *d_ring = nullptr;
         unsigned long long *d_sub = nullptr;
+        uint64_t *d_heap = nullptr;
+        uint64_t heap_words = 0;
         bool any_deep = false;
         for (const bcdev::ActiveRoot &a : aroots) any_deep = any_deep || cjobs[a.job].pA >= 5;
         if (any_deep && split_rows != 0 && split_rows != 0xffffffffu) {
             uint64_t cap = 1ull << 22;
             if (ex.fixed || mem.cap) cap = std::min<uint64_t>(cap, mem.room() / 4 / sizeof(uint4));
-            if (cap >= 1024) {
+            uint64_t hw = 1ull << 26;
+            if (ex.fixed || mem.cap) hw = std::min<uint64_t>(hw, mem.room() / 4 / 8);
+            if (cap >= 1024 && hw >= 4096) {
                 BC_HIP(mem.get(&d_ring, cap));
-                BC_HIP(mem.get(&d_sub, 2));
+                BC_HIP(mem.get(&d_sub, 4));
+                BC_HIP(mem.get(&d_heap, hw));
                 BC_HIP(fill_u32((uint32_t *)d_ring, cap * 4, 0u, st));
-                BC_HIP(fill_u32((uint32_t *)d_sub, 4, 0u, st));
+                BC_HIP(fill_u32((uint32_t *)d_sub, 8, 0u, st));
                 split_cap = (uint32_t)cap;
+                heap_words = hw;
             }
         }
         // Enumeration grid: waves_per_cu wavefronts per CU; each wave owns a
@@ -1518,8 +1535,16 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         prm.split_rows = split_rows ? split_rows : 256u;
         prm.split_cap = split_cap;
         prm.ring = d_ring;
+        if (instrument) {
+            BC_HIP(mem.get(&d_wave_clock, 2ull * blocks * bcdev::kWavesPerBlock));
+            BC_HIP(fill_u32((uint32_t *)d_wave_clock, 4ull * blocks * bcdev::kWavesPerBlock, 0u, st));
+            n_wave_clock = (uint64_t)blocks * bcdev::kWavesPerBlock;
+        }
+        prm.wave_clock = d_wave_clock;
         prm.sub_head = d_sub;
         prm.sub_tail = d_sub ? d_sub + 1 : nullptr;
+        prm.split_heap = d_heap;
+        prm.split_heap_words = heap_words;
         prm.pool = d_pool;
         prm.slab = d_slab;
         prm.slab_words = slab_need;
@@ -1629,6 +1654,23 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         stats->candidate_edges = cand_edges;
         stats->row_words = pool_words;
         stats->scratch_bytes = mem.total;
+        if (n_wave_clock) {
+            // device clock at 100 MHz: 1e5 ticks per millisecond
+            std::vector<unsigned long long> wc(2 * n_wave_clock);
+            if (hipMemcpy(wc.data(), d_wave_clock, wc.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
+                unsigned long long s0 = ~0ull, e0 = ~0ull, e1 = 0;
+                for (uint64_t w = 0; w < n_wave_clock; ++w) {
+                    if (!wc[2 * w + 1]) continue;
+                    s0 = std::min(s0, wc[2 * w]);
+                    e0 = std::min(e0, wc[2 * w + 1]);
+                    e1 = std::max(e1, wc[2 * w + 1]);
+                }
+                if (e1) {
+                    stats->ms_wave_makespan = (double)(e1 - s0) / 1e5;
+                    stats->ms_wave_spread = (double)(e1 - e0) / 1e5;
+                }
+            }
+        }
         for (size_t i = 0; i < ns; ++i) {
             const bcdev::Slot &sl = hs[spec_jobs[i][0]];
             stats->pair_ops += sl.pair_ops;
@@ -1815,6 +1857,268 @@ extern "C" bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t
         }
     }
     *tuned = cur;
+    return BC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BCPar (Algorithm 3, Section VI): roots of one anchor side grouped so that
+// each group's closure -- the roots, their oriented 2-hop candidates and the
+// neighbourhoods of both -- fits a memory budget; each group is then counted
+// on its closure alone, and the groups' counts add up to the whole count.
+
+namespace {
+
+// Oriented 2-hop candidates of every vertex of side a: the w ranked after u
+// sharing at least k neighbours with u (the set a root's search draws from),
+// by wedge counting on the host; threads take roots in chunks.
+void oriented_candidates(const bc_graph *g, int a, uint32_t k, const std::vector<uint32_t> &adj_a,
+                         const std::vector<uint32_t> &adj_b, std::vector<uint64_t> &off, std::vector<uint32_t> &ids)
+{
+    const Side &A = g->side[a], &B = g->side[1 - a];
+    const uint64_t n = A.n;
+    std::vector<std::vector<uint32_t>> part(n);
+    std::atomic<uint64_t> next{0};
+    auto work = [&] {
+        std::vector<uint32_t> cnt(n, 0), touched;
+        for (;;) {
+            const uint64_t b = next.fetch_add(64), e = std::min(n, b + 64);
+            if (b >= n) break;
+            for (uint64_t u = b; u < e; ++u) {
+                touched.clear();
+                for (uint64_t x = A.h_ptr[u]; x < A.h_ptr[u + 1]; ++x) {
+                    const uint32_t v = adj_a[x];
+                    for (uint64_t y = B.h_ptr[v]; y < B.h_ptr[v + 1]; ++y) {
+                        const uint32_t w = adj_b[y];
+                        if (w > u && cnt[w]++ == 0) touched.push_back(w);
+                    }
+                }
+                std::vector<uint32_t> &out = part[u];
+                for (uint32_t w : touched) {
+                    if (cnt[w] >= k) out.push_back(w);
+                    cnt[w] = 0;
+                }
+                std::sort(out.begin(), out.end());
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < host_threads(); ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+    off.assign(n + 1, 0);
+    for (uint64_t u = 0; u < n; ++u) off[u + 1] = off[u] + part[u].size();
+    ids.resize(off[n]);
+    for (uint64_t u = 0; u < n; ++u) std::copy(part[u].begin(), part[u].end(), ids.begin() + off[u]);
+}
+
+bc_status read_rows(const bc_graph *g, int side, std::vector<uint32_t> &adj)
+{
+    adj.resize(g->nnz);
+    hipStream_t st = own_stream();
+    if (!st) return set_error(BC_E_DEVICE, "could not create a HIP stream");
+    if (g->nnz) BC_HIP(hipMemcpyAsync(adj.data(), g->side[side].d_adj, g->nnz * 4, hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    return BC_OK;
+}
+
+bc_status partition_args(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor, uint32_t *kA)
+{
+    if (!g) return set_error(BC_E_INVALID_ARG, "NULL graph");
+    if (bc_status s = check_pq(p, q)) return s;
+    if (anchor != BC_ANCHOR_U && anchor != BC_ANCHOR_V)
+        return set_error(BC_E_INVALID_ARG, "anchor must be BC_ANCHOR_U or BC_ANCHOR_V");
+    const uint32_t pA = anchor == BC_ANCHOR_U ? p : q;
+    *kA = anchor == BC_ANCHOR_U ? q : p;
+    if (pA < 3) return set_error(BC_E_INVALID_ARG, "partitioned counts need a depth of at least 3 on the anchor side");
+    return BC_OK;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_partition(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor, uint64_t budget_bytes,
+                                  uint32_t *part_of_rank, uint32_t *n_parts)
+{
+    g_last_error.clear();
+    uint32_t kA = 0;
+    if (bc_status s = partition_args(g, p, q, anchor, &kA)) return s;
+    if (!part_of_rank || !n_parts) return set_error(BC_E_INVALID_ARG, "bc_partition: NULL argument");
+    const int a = anchor;
+    const Side &A = g->side[a];
+    const uint64_t n = A.n;
+    std::vector<uint32_t> adj_a, adj_b;
+    if (bc_status s = read_rows(g, a, adj_a)) return s;
+    if (bc_status s = read_rows(g, 1 - a, adj_b)) return s;
+    std::vector<uint64_t> coff;
+    std::vector<uint32_t> cids;
+    oriented_candidates(g, a, kA, adj_a, adj_b, coff, cids);
+    // w(u) = |N(u)| + |N_2(u)| entries of 4 bytes; avg_w(u) over u's candidates
+    std::vector<uint64_t> w(n);
+    for (uint64_t u = 0; u < n; ++u) w[u] = 4 * ((A.h_ptr[u + 1] - A.h_ptr[u]) + (coff[u + 1] - coff[u]));
+    std::vector<double> avg(n, 0.0);
+    for (uint64_t u = 0; u < n; ++u) {
+        const uint64_t c = coff[u + 1] - coff[u];
+        double sum = 0;
+        for (uint64_t x = coff[u]; x < coff[u + 1]; ++x) sum += (double)w[cids[x]];
+        avg[u] = c ? sum / (double)c : 0.0;
+    }
+    // reverse candidate lists: roots whose closure holds w (N_in of Algorithm 3)
+    std::vector<uint64_t> roff(n + 1, 0);
+    for (uint32_t x : cids) roff[x + 1]++;
+    for (uint64_t u = 0; u < n; ++u) roff[u + 1] += roff[u];
+    std::vector<uint32_t> rids(cids.size());
+    {
+        std::vector<uint64_t> fill(roff.begin(), roff.end() - 1);
+        for (uint64_t u = 0; u < n; ++u)
+            for (uint64_t x = coff[u]; x < coff[u + 1]; ++x) rids[fill[cids[x]]++] = (uint32_t)u;
+    }
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return avg[x] > avg[y]; });
+    const uint32_t kNone = 0xffffffffu;
+    std::vector<uint32_t> part(n, kNone);
+    std::vector<uint32_t> in_closure(n, kNone);   // partition whose closure holds the vertex
+    std::vector<double> prio(n, 0.0);
+    uint32_t np = 0;
+    size_t next = 0;
+    for (;;) {
+        while (next < n && part[order[next]] != kNone) ++next;
+        if (next == n) break;
+        // a new partition from the unassigned root of highest average weight
+        const uint32_t id = np++;
+        uint64_t cost = 0;
+        std::vector<uint32_t> touched_q;   // roots given a priority in this partition
+        std::priority_queue<std::pair<double, uint32_t>> Q;
+        auto add_member = [&](uint32_t x) {   // closure member x: its cost, and the roots that share it
+            if (in_closure[x] == id) return;
+            in_closure[x] = id;
+            cost += w[x];
+            for (uint64_t y = roff[x]; y < roff[x + 1]; ++y) {
+                const uint32_t v = rids[y];
+                if (part[v] != kNone) continue;
+                if (prio[v] == 0.0) touched_q.push_back(v);
+                prio[v] += (double)w[v];
+                Q.push({prio[v], v});
+            }
+        };
+        auto closure_cost = [&](uint32_t u) {   // cost that adding root u would add
+            uint64_t c = in_closure[u] == id ? 0 : w[u];
+            for (uint64_t x = coff[u]; x < coff[u + 1]; ++x)
+                if (in_closure[cids[x]] != id) c += w[cids[x]];
+            return c;
+        };
+        uint32_t u = order[next];
+        part[u] = id;
+        add_member(u);
+        for (uint64_t x = coff[u]; x < coff[u + 1]; ++x) add_member(cids[x]);
+        for (;;) {
+            // the unassigned root sharing the most (weighted) with the closure,
+            // else the next root of the global order
+            uint32_t v = kNone;
+            while (!Q.empty()) {
+                const auto top = Q.top();
+                Q.pop();
+                if (part[top.second] == kNone && top.first == prio[top.second]) {
+                    v = top.second;
+                    break;
+                }
+            }
+            if (v == kNone) {
+                size_t t = next;
+                while (t < n && part[order[t]] != kNone) ++t;
+                if (t == n) break;
+                v = order[t];
+            }
+            if (cost + closure_cost(v) > budget_bytes) break;   // the partition is full
+            part[v] = id;
+            add_member(v);
+            for (uint64_t x = coff[v]; x < coff[v + 1]; ++x) add_member(cids[x]);
+        }
+        for (uint32_t v : touched_q) prio[v] = 0.0;
+    }
+    for (uint64_t u = 0; u < n; ++u) part_of_rank[u] = part[u];
+    *n_parts = np;
+    return BC_OK;
+}
+
+extern "C" bc_status bc_count_partition(const bc_graph *g, uint32_t p, uint32_t q, int32_t anchor,
+                                        const uint32_t *part_of_rank, uint32_t part, const bc_opts *opts,
+                                        bc_u128 *out, uint64_t *closure_edges)
+{
+    g_last_error.clear();
+    uint32_t kA = 0;
+    if (bc_status s = partition_args(g, p, q, anchor, &kA)) return s;
+    if (!part_of_rank || !out) return set_error(BC_E_INVALID_ARG, "bc_count_partition: NULL argument");
+    if (bc_status s = check_opts(opts)) return s;
+    const int a = anchor;
+    const Side &A = g->side[a], &B = g->side[1 - a];
+    std::vector<uint32_t> adj_a, adj_b;
+    if (bc_status s = read_rows(g, a, adj_a)) return s;
+    if (bc_status s = read_rows(g, 1 - a, adj_b)) return s;
+    std::vector<uint64_t> coff;
+    std::vector<uint32_t> cids;
+    oriented_candidates(g, a, kA, adj_a, adj_b, coff, cids);
+    // closure: the partition's roots and their candidates, in rank order
+    std::vector<uint8_t> in(A.n, 0);
+    for (uint64_t u = 0; u < A.n; ++u)
+        if (part_of_rank[u] == part) {
+            in[u] = 1;
+            for (uint64_t x = coff[u]; x < coff[u + 1]; ++x) in[cids[x]] = 1;
+        }
+    std::vector<uint32_t> xs;
+    for (uint64_t u = 0; u < A.n; ++u)
+        if (in[u]) xs.push_back((uint32_t)u);
+    // the other side: every neighbour of the closure
+    std::vector<uint32_t> ymap(B.n, 0xffffffffu), ys;
+    for (uint32_t x : xs)
+        for (uint64_t e = A.h_ptr[x]; e < A.h_ptr[x + 1]; ++e) {
+            const uint32_t v = adj_a[e];
+            if (ymap[v] == 0xffffffffu) {
+                ymap[v] = (uint32_t)ys.size();
+                ys.push_back(v);
+            }
+        }
+    // subgraph CSRs: anchor side rows are the closure vertices in rank order
+    // (their ids in the subgraph), with their whole neighbourhoods, so degrees
+    // and the (degree, id) order among them are those of g
+    std::vector<uint64_t> pa(xs.size() + 1, 0), pb(ys.size() + 1, 0);
+    std::vector<uint32_t> ia, ib;
+    for (size_t i = 0; i < xs.size(); ++i) {
+        for (uint64_t e = A.h_ptr[xs[i]]; e < A.h_ptr[xs[i] + 1]; ++e) ia.push_back(ymap[adj_a[e]]);
+        pa[i + 1] = ia.size();
+    }
+    std::vector<uint64_t> degb(ys.size() + 1, 0);
+    for (uint32_t y : ia) degb[y + 1]++;
+    for (size_t y = 0; y < ys.size(); ++y) degb[y + 1] += degb[y];
+    ib.resize(ia.size());
+    {
+        std::vector<uint64_t> fill(degb.begin(), degb.end() - 1);
+        for (size_t i = 0; i < xs.size(); ++i)
+            for (uint64_t e = pa[i]; e < pa[i + 1]; ++e) ib[fill[ia[e]]++] = (uint32_t)i;
+    }
+    pb = degb;
+    bc_csr cu{xs.size(), ys.size(), ia.size(), pa.data(), ia.data()};
+    bc_csr cv{ys.size(), xs.size(), ib.size(), pb.data(), ib.data()};
+    bc_opts bo{};
+    if (opts) bo = *opts;
+    bo.struct_size = sizeof(bc_opts);
+    bo.order_key = BC_ORDER_DEGREE;
+    bc_graph *sub = nullptr;
+    bc_status s = a == 0 ? bc_build(&cu, &cv, &bo, &sub) : bc_build(&cv, &cu, &bo, &sub);
+    if (s != BC_OK) return s;
+    // the partition's roots, by their rank in the subgraph (= position in xs)
+    std::vector<uint8_t> mask(xs.size(), 0);
+    for (size_t i = 0; i < xs.size(); ++i) mask[sub->side[a].rank_of[i]] = part_of_rank[xs[i]] == part;
+    JobSpec js{sub, p, q, anchor, 0, 0, false, opts_deadline(opts)};
+    js.root_mask = &mask;
+    std::vector<JobSpec> sp{js};
+    std::vector<bc_u128> res;
+    std::vector<bc_status> ist;
+    s = run_jobs(sp, &bo, res, ist, nullptr);
+    bc_free(sub);
+    if (s != BC_OK) return s;
+    if (ist[0] != BC_OK) return ist[0];
+    *out = res[0];
+    if (closure_edges) *closure_edges = ia.size();
     return BC_OK;
 }
 

@@ -1594,14 +1594,17 @@ __device__ __forceinline__ uint64_t cycles() { return __builtin_amdgcn_s_memtime
 // `rows` rows queues one subtask per kept row in a ring that wavefronts drain
 // once the task queue is empty (runtime load balancing, Section V-C).
 struct SplitCtx {
-    uint4 *ring;                    // {root index, i, j, ready}; ready is stored last
+    uint4 *ring;                    // {heap offset lo, hi, child row, ready}; ready is stored last
     unsigned long long *tail;       // entries reserved so far
+    uint64_t *heap;                 // split tasks' level-2 blocks, each after a 4-word header
+    unsigned long long *heap_used;  // words of the heap taken so far
+    uint64_t heap_cap;              // heap words
     uint32_t cap;                   // ring entries
     uint32_t rows;                  // split threshold on the kept rows
     uint32_t root_idx;              // index of the task's root in the active-root list
 };
 
-constexpr uint32_t kNoJ = 0xffffffffu;   // "no third vertex": a (root, second vertex) task
+constexpr uint32_t kNoJ = 0xffffffffu;   // no restriction to one child
 
 // Reserves n consecutive ring entries (lane 0 decides, every lane learns);
 // ~0 when the ring cannot hold them.
@@ -1623,21 +1626,41 @@ __device__ unsigned long long ring_reserve(const SplitCtx &sp, uint32_t n)
 
 // Publishes one ring entry: the payload first, then the ready word with
 // release order, so that a reader that sees ready also sees the payload.
-__device__ __forceinline__ void ring_put(uint4 *e, uint32_t r, uint32_t i, uint32_t j)
+__device__ __forceinline__ void ring_put(uint4 *e, uint64_t off, uint32_t a)
 {
-    e->x = r;
-    e->y = i;
-    e->z = j;
+    e->x = (uint32_t)off;
+    e->y = (uint32_t)(off >> 32);
+    e->z = a;
     __hip_atomic_store(&e->w, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One task: the node {u, c_i} of the search tree (j == kNoJ), or, for a
-// subtask of a split task, the node {u, c_i, c_j} (its common neighbours are
-// rows i and j ANDed, its candidates are the rows after j, and pA is one less:
-// the node is then handled exactly like a task of a query one level shallower).
-__device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, uint32_t j, uint32_t pA,
-                         const uint64_t *pool, Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct,
-                         bool instrument, bool triple, const SplitCtx *sp, bool *cap_fail, bool *timed_out)
+// Takes n heap words (lane 0 decides, every lane learns); ~0 when the heap
+// cannot hold them.
+__device__ unsigned long long heap_take(const SplitCtx &sp, uint64_t n)
+{
+    unsigned long long got = ~0ull;
+    if (lane_id() == 0) {
+        unsigned long long cur = __hip_atomic_load(sp.heap_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (cur + n <= sp.heap_cap) {
+            if (__hip_atomic_compare_exchange_strong(sp.heap_used, &cur, cur + n, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                got = cur;
+                break;
+            }
+        }
+    }
+    return bcast64(got, 0);
+}
+
+__device__ void dfs_level2(const Job &jb, uint32_t jidx, const uint64_t *blk2, uint32_t stride2, uint32_t m2,
+                           uint32_t W2, uint32_t s2n, uint32_t only_child, Arena &ar, uint64_t *stack, Table &tb,
+                           Acc &acc, Counters &ct, bool instrument, bool triple, bool *cap_fail, bool *timed_out,
+                           uint64_t t0);
+
+// One task: the node {u, c_i} of the search tree.
+__device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, const uint64_t *pool,
+                         Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument, bool triple,
+                         const SplitCtx *sp, bool *cap_fail, bool *timed_out)
 {
     const uint32_t ln = lane_id();
     const uint32_t u = rt.root;
@@ -1645,12 +1668,12 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     const uint32_t W1 = (du + 63) >> 6;
     const uint32_t k = rt.k;
     glb_u64 *base = (glb_u64 *)(pool + rt.pool_off);   // the root's rows (global: typed loads)
-    const uint32_t q = jb.qA;
+    const uint32_t q = jb.qA, pA = jb.pA;
     uint64_t t0 = instrument ? cycles() : 0;
 
-    const uint32_t s = j == kNoJ ? i : j;   // the candidates are the rows after s
+    const uint32_t s = i;   // the candidates are the rows after i
     const uint32_t rem = k - s - 1;
-    if (j == kNoJ && pA == 3 && W1 <= kTileWords && du <= jb.n_u28 && table_ready(tb, jb, jidx, du + 1)) {
+    if (pA == 3 && W1 <= kTileWords && du <= jb.n_u28 && table_ready(tb, jb, jidx, du + 1)) {
         // the root's leaves {u, c_a, c_b} are the pair sum over its rows:
         // task i = 16 I takes row block I on the matrix cores, the root's
         // other tasks have nothing left to do
@@ -1683,7 +1706,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     uint64_t *nzt = nullptr;
     if (W1 == 1) {
         // one-word root: nothing to scan or tabulate
-        const uint64_t x = base[i] & (j == kNoJ ? ~0ull : base[j]);
+        const uint64_t x = base[i];
         const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
         const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
         s0 = ((uint64_t)hi << 32) | lo;
@@ -1699,8 +1722,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         uint64_t *s2 = arena_alloc(ar, 2ull * W1, cap_fail);
         if (!s2) return;
         uint64_t *pre = s2 + W1;
-        for (uint32_t w = ln; w < W1; w += kWaveSize)
-            s2[w] = base[(uint64_t)w * k + i] & (j == kNoJ ? ~0ull : base[(uint64_t)w * k + j]);
+        for (uint32_t w = ln; w < W1; w += kWaveSize) s2[w] = base[(uint64_t)w * k + i];
         wave_sync();
         uint32_t running = 0;
         for (uint32_t x0 = 0; x0 < W1; x0 += kWaveSize) {
@@ -1895,62 +1917,65 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         t0 = t1;
     }
     if (m2 < pA - 2) return;
-    if (sp && j == kNoJ && pA >= 5 && m2 > sp->rows) {
-        // Heavy task: queue the nodes {u, c_i, c_b} of its kept rows b as
-        // subtasks.  The kept rows are found again (the same integer test
-        // as above, so the same m2 rows); entries the ring cannot take are
-        // not reserved and the task continues here instead.
-        const unsigned long long at = ring_reserve(*sp, m2);
+    // Heavy task (p_A >= 5): its level-2 block goes to the split heap (4-word
+    // header, then the block with stride m2) and each child row a that can
+    // still complete L becomes a subtask in the ring, to be finished by
+    // whichever wavefront takes it; if the heap or the ring is full, the task
+    // carries on here.
+    if (sp && pA >= 5 && m2 > sp->rows && !(triple && m2 <= kTripleRows)) {
+        const uint32_t n_sub = m2 - (pA - 3);   // children a <= m2 - (pA - 2)
+        const unsigned long long off = heap_take(*sp, 4 + (uint64_t)m2 * W2);
+        const unsigned long long at = off != ~0ull ? ring_reserve(*sp, n_sub) : ~0ull;
         if (at != ~0ull) {
-            uint32_t put = 0;
-            for (uint32_t b0 = s + 1; b0 < k; b0 += kWaveSize) {
-                const uint32_t b = b0 + ln;
-                const uint32_t bb = b < k ? b : s;
-                uint32_t n = 0;
-                if (nz <= 2) {
-                    if (nz > 0) n += __popcll(s0 & base[(uint64_t)w0 * k + bb]);
-                    if (nz > 1) n += __popcll(s1 & base[(uint64_t)w1 * k + bb]);
-                } else {
-                    for (uint32_t e = 0; e < nz; ++e) {
-                        const uint32_t w = (uint32_t)nzt[8ull * e + 7];
-                        n += __popcll(nzt[8ull * e] & base[(uint64_t)w * k + bb]);
-                    }
-                }
-                const bool keep = b < k && n >= q;
-                const uint64_t mask = __ballot(keep);
-                const uint32_t slot = put + mbcnt64(mask);
-                if (keep && slot < m2) ring_put(sp->ring + at + slot, sp->root_idx, i, b);
-                put += (uint32_t)__popcll(mask);
+            uint64_t *hdr = sp->heap + off;
+            if (ln == 0) {
+                hdr[0] = sp->root_idx;
+                hdr[1] = i;
+                hdr[2] = (uint64_t)m2 | ((uint64_t)W2 << 32);
+                hdr[3] = s2n;
             }
-            // (put == m2; should it differ, the reserved entries left over are
-            // published as empty so that no reader waits on them)
-            for (uint32_t x = put + ln; x < m2; x += kWaveSize) ring_put(sp->ring + at + x, sp->root_idx, i, kNoJ);
-            if (put != m2) *cap_fail = true;
-            if (instrument) ct.filter_words += (unsigned long long)rem * nz;
+            for (uint32_t w = 0; w < W2; ++w)
+                for (uint32_t x = ln; x < m2; x += kWaveSize)
+                    hdr[4 + (uint64_t)w * m2 + x] = ar.holds(blk2) ? blk2[(uint64_t)w * rem + x]
+                                                                   : row_word<false>(blk2, (uint64_t)w * rem + x);
+            // the block must be visible before any entry naming it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (uint32_t x = ln; x < n_sub; x += kWaveSize) ring_put(sp->ring + at + x, off, x);
+            if (instrument) ct.cyc_compact += cycles() - t0;
             return;
         }
+        // (a heap block taken without ring room stays unused until the launch ends)
     }
+    dfs_level2(jb, jidx, blk2, rem, m2, W2, s2n, kNoJ, ar, stack, tb, acc, ct, instrument, triple, cap_fail, timed_out,
+               t0);
+}
+
+// The search below a level-2 node {u, c_i} whose block holds m2 rows of W2
+// words (column-major, stride2): pair sums for p_A = 4, else the DFS over
+// levels 2 .. pA-3, the node at level pA-2 finished by pair_sum (small nodes
+// at level pA-3 by the three-level sweep).  only_child != kNoJ restricts the
+// level-2 loop to that one child row (a subtask of a split task).
+__device__ void dfs_level2(const Job &jb, uint32_t jidx, const uint64_t *blk2, uint32_t stride2, uint32_t m2,
+                           uint32_t W2, uint32_t s2n, uint32_t only_child, Arena &ar, uint64_t *stack, Table &tb,
+                           Acc &acc, Counters &ct, bool instrument, bool triple, bool *cap_fail, bool *timed_out,
+                           uint64_t t0)
+{
+    const uint32_t q = jb.qA, pA = jb.pA;
     if (pA == 4) {
-        const uint32_t G = pair_sum(blk2, ar.holds(blk2), rem, m2, W2, s2n, jb, jidx, tb, acc);
+        const uint32_t G = pair_sum(blk2, ar.holds(blk2), stride2, m2, W2, s2n, jb, jidx, tb, acc);
         if (instrument) count_pairs(ct, m2, W2, G);
         if (instrument) ct.cyc_pair += cycles() - t0;
         return;
     }
-
-    // DFS over levels 2 .. pA-3; the node at level pA-2 is finished by pair_sum.
-    // stack[4*d + 0] = block offset (bit 63: in slab), [1] = stride | m << 32,
+    // stack[4*d + 0] = the level's block (pointer), [1] = stride | m << 32,
     // [2] = cursor, [3] = arena marks (lds_used | slab_used << 32).
-    auto enc_ptr = [&](const uint64_t *p) -> uint64_t {
-        return (p >= ar.lds && p < ar.lds + ar.lds_cap) ? (uint64_t)(p - ar.lds)
-                                                        : ((uint64_t)(p - ar.slab) | (1ull << 63));
-    };
-    auto dec_ptr = [&](uint64_t e) -> uint64_t * {
-        return (e >> 63) ? ar.slab + (e & ~(1ull << 63)) : ar.lds + e;
-    };
+    auto enc_ptr = [&](const uint64_t *p) -> uint64_t { return (uint64_t)(uintptr_t)p; };
+    auto dec_ptr = [&](uint64_t e) -> const uint64_t * { return (const uint64_t *)(uintptr_t)e; };
+    const uint32_t a_end = only_child == kNoJ ? 0xffffffffu : only_child + 1;
     uint32_t d = 2;
     stack[4 * 2 + 0] = enc_ptr(blk2);
-    stack[4 * 2 + 1] = (uint64_t)rem | ((uint64_t)m2 << 32);
-    stack[4 * 2 + 2] = 0;
+    stack[4 * 2 + 1] = (uint64_t)stride2 | ((uint64_t)m2 << 32);
+    stack[4 * 2 + 2] = only_child == kNoJ ? 0 : only_child;
     stack[4 * 2 + 3] = 0;
     for (;;) {
         if (past_deadline(jb.deadline)) {
@@ -2000,8 +2025,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
             ar.slab_used = mark >> 32;
             a = m;   // exhausted: pop below
         }
-        // row a needs pA - d - 1 more rows after it
-        if ((int64_t)a > (int64_t)m - (int64_t)pA + (int64_t)d) {
+        // row a needs pA - d - 1 more rows after it (a subtask does one level-2 child)
+        if ((int64_t)a > (int64_t)m - (int64_t)pA + (int64_t)d || (d == 2 && a >= a_end)) {
             if (d == 2) break;
             // pop: release this level's block
             const uint64_t mk = stack[4 * d + 3];
@@ -2099,9 +2124,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     // subtasks can appear.
     const bool split = prm.split_cap != 0;
     const unsigned long long kProducer = 1ull << 40, kPopMask = kProducer - 1;
+    const unsigned long long t_start = instrument ? __builtin_amdgcn_s_memrealtime() : 0ull;
     SplitCtx sp;
     sp.ring = prm.ring;
     sp.tail = prm.sub_tail;
+    sp.heap = prm.split_heap;
+    sp.heap_used = prm.sub_head + 2;
+    sp.heap_cap = prm.split_heap_words;
     sp.cap = prm.split_cap;
     sp.rows = prm.split_rows;
     sp.root_idx = 0;
@@ -2135,8 +2164,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             bool cap_fail = false, timed_out = past_deadline(jb.deadline);
             sp.root_idx = r;
             if (!timed_out)
-                run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), kNoJ, jb.pA, prm.pool, arena, stack, tb, acc,
-                         ct, instrument, prm.triple != 0, split ? &sp : nullptr, &cap_fail, &timed_out);
+                run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct, instrument,
+                         prm.triple != 0, split ? &sp : nullptr, &cap_fail, &timed_out);
             if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
             if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
         }
@@ -2181,17 +2210,20 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             __builtin_amdgcn_s_sleep(4);
         }
         if (state == 2) break;
-        uint32_t er = 0, ei = 0, ej = 0;
+        uint32_t elo = 0, ehi = 0, ea = 0;
         if (ln == 0) {
             const uint4 e = prm.ring[h];
-            er = e.x;
-            ei = e.y;
-            ej = e.z;
+            elo = e.x;
+            ehi = e.y;
+            ea = e.z;
         }
-        er = (uint32_t)__builtin_amdgcn_readfirstlane(er);
-        ei = (uint32_t)__builtin_amdgcn_readfirstlane(ei);
-        ej = (uint32_t)__builtin_amdgcn_readfirstlane(ej);
-        if (ej == kNoJ) continue;   // an empty entry
+        elo = (uint32_t)__builtin_amdgcn_readfirstlane(elo);
+        ehi = (uint32_t)__builtin_amdgcn_readfirstlane(ehi);
+        ea = (uint32_t)__builtin_amdgcn_readfirstlane(ea);
+        // the parent's level-2 block and its header (written before the entry was published)
+        const uint64_t *hdr = prm.split_heap + (((uint64_t)ehi << 32) | elo);
+        const uint32_t er = (uint32_t)hdr[0];
+        const uint32_t hm2 = (uint32_t)hdr[2], hW2 = (uint32_t)(hdr[2] >> 32), hs2n = (uint32_t)hdr[3];
         const ActiveRoot rt = prm.roots[er];
         if (rt.job != cur_job) {
             if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
@@ -2199,13 +2231,20 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
         }
         const Job jb = prm.jobs[rt.job];
         bool cap_fail = false, timed_out = past_deadline(jb.deadline);
-        if (!timed_out)
-            run_task(jb, rt.job, rt, ei, ej, jb.pA - 1, prm.pool, arena, stack, tb, acc, ct, instrument,
-                     prm.triple != 0, nullptr, &cap_fail, &timed_out);
+        if (!timed_out) {
+            Arena ar = arena;
+            dfs_level2(jb, rt.job, hdr + 4, hm2, hm2, hW2, hs2n, ea, ar, stack, tb, acc, ct, instrument,
+                       prm.triple != 0, &cap_fail, &timed_out, instrument ? cycles() : 0);
+        }
         if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
         if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
     }
     if (cur_job != 0xffffffffu) enum_flush(prm.slots, prm.jobs[cur_job].slot, acc, ct, instrument);
+    if (instrument && prm.wave_clock && ln == 0) {
+        // when this wavefront started and ran out of work (load balance)
+        prm.wave_clock[2 * wave_global] = t_start;
+        prm.wave_clock[2 * wave_global + 1] = __builtin_amdgcn_s_memrealtime();
+    }
 }
 
 hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream)
