@@ -26,7 +26,7 @@
 
 namespace bcdev {
 
-constexpr uint32_t kLdsWordsPerWave = 600;    // LDS arena per wavefront (64-bit words)
+constexpr uint32_t kLdsWordsPerWave = 1024;   // LDS arena per wavefront (64-bit words): 3 blocks of 4 waves fill 160 KiB
 constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of the tiled leaf sum
 constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
@@ -1652,12 +1652,14 @@ __device__ unsigned long long heap_take(const SplitCtx &sp, uint64_t n)
     return bcast64(got, 0);
 }
 
-__device__ void dfs_level2(const Job &jb, uint32_t jidx, const uint64_t *blk2, uint32_t stride2, uint32_t m2,
-                           uint32_t W2, uint32_t s2n, uint32_t only_child, Arena &ar, uint64_t *stack, Table &tb,
-                           Acc &acc, Counters &ct, bool instrument, bool triple, bool *cap_fail, bool *timed_out,
-                           uint64_t t0);
+__device__ __attribute__((always_inline)) inline void dfs_level2(
+    const Job &jb, uint32_t jidx, const uint64_t *blk2, uint32_t stride2, uint32_t m2, uint32_t W2, uint32_t s2n,
+    uint32_t only_child, Arena &ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument, bool triple,
+    bool *cap_fail, bool *timed_out, uint64_t t0);
 
-// One task: the node {u, c_i} of the search tree.
+// One task: the node {u, c_i} of the search tree.  SPLIT compiles in the
+// hand-off of heavy tasks to the subtask ring; without it sp is unused.
+template <bool SPLIT>
 __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uint32_t i, const uint64_t *pool,
                          Arena ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument, bool triple,
                          const SplitCtx *sp, bool *cap_fail, bool *timed_out)
@@ -1922,7 +1924,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
     // still complete L becomes a subtask in the ring, to be finished by
     // whichever wavefront takes it; if the heap or the ring is full, the task
     // carries on here.
-    if (sp && pA >= 5 && m2 > sp->rows && !(triple && m2 <= kTripleRows)) {
+    if constexpr (SPLIT) {
+    if (pA >= 5 && m2 > sp->rows && !(triple && m2 <= kTripleRows)) {
         const uint32_t n_sub = m2 - (pA - 3);   // children a <= m2 - (pA - 2)
         const unsigned long long off = heap_take(*sp, 4 + (uint64_t)m2 * W2);
         const unsigned long long at = off != ~0ull ? ring_reserve(*sp, n_sub) : ~0ull;
@@ -1946,6 +1949,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         }
         // (a heap block taken without ring room stays unused until the launch ends)
     }
+    }
     dfs_level2(jb, jidx, blk2, rem, m2, W2, s2n, kNoJ, ar, stack, tb, acc, ct, instrument, triple, cap_fail, timed_out,
                t0);
 }
@@ -1955,10 +1959,10 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
 // levels 2 .. pA-3, the node at level pA-2 finished by pair_sum (small nodes
 // at level pA-3 by the three-level sweep).  only_child != kNoJ restricts the
 // level-2 loop to that one child row (a subtask of a split task).
-__device__ void dfs_level2(const Job &jb, uint32_t jidx, const uint64_t *blk2, uint32_t stride2, uint32_t m2,
-                           uint32_t W2, uint32_t s2n, uint32_t only_child, Arena &ar, uint64_t *stack, Table &tb,
-                           Acc &acc, Counters &ct, bool instrument, bool triple, bool *cap_fail, bool *timed_out,
-                           uint64_t t0)
+__device__ __attribute__((always_inline)) inline void dfs_level2(
+    const Job &jb, uint32_t jidx, const uint64_t *blk2, uint32_t stride2, uint32_t m2, uint32_t W2, uint32_t s2n,
+    uint32_t only_child, Arena &ar, uint64_t *stack, Table &tb, Acc &acc, Counters &ct, bool instrument, bool triple,
+    bool *cap_fail, bool *timed_out, uint64_t t0)
 {
     const uint32_t q = jb.qA, pA = jb.pA;
     if (pA == 4) {
@@ -2086,6 +2090,9 @@ __device__ void enum_flush(Slot *slots, uint32_t slot, Acc &acc, Counters &ct, b
 }
 
 // Three waves per SIMD (12 per CU): the register budget is capped at 168 VGPRs.
+// SPLIT = runtime splitting of heavy tasks (the subtask ring and its drain);
+// the plain variant carries none of that code.
+template <bool SPLIT>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_enumerate(
     EnumParams prm)
 {
@@ -2122,7 +2129,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     // leaves that count, with release order after its ring entries, once the
     // chunk is done; the drain below uses the count to know when no more
     // subtasks can appear.
-    const bool split = prm.split_cap != 0;
+    constexpr bool split = SPLIT;
     const unsigned long long kProducer = 1ull << 40, kPopMask = kProducer - 1;
     const unsigned long long t_start = instrument ? __builtin_amdgcn_s_memrealtime() : 0ull;
     SplitCtx sp;
@@ -2164,8 +2171,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
             bool cap_fail = false, timed_out = past_deadline(jb.deadline);
             sp.root_idx = r;
             if (!timed_out)
-                run_task(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct, instrument,
-                         prm.triple != 0, split ? &sp : nullptr, &cap_fail, &timed_out);
+                run_task<SPLIT>(jb, rt.job, rt, (uint32_t)(t - rt.task_begin), prm.pool, arena, stack, tb, acc, ct,
+                                instrument, prm.triple != 0, &sp, &cap_fail, &timed_out);
             if (cap_fail && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_CAPACITY);
             if (timed_out && ln == 0) atomicOr(&prm.slots[jb.slot].flags, FLAG_TIMEOUT);
         }
@@ -2181,7 +2188,7 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     // reserved count is final: an index at or past it, or past the ring, will
     // never be filled and the wavefront is done.  Producers only run popped
     // chunks, so every wait ends when they finish their (finite) tasks.
-    while (split) {
+    while (SPLIT) {
         unsigned long long h = 0;
         if (ln == 0) h = atomicAdd(prm.sub_head, 1ull);
         h = bcast64(h, 0);
@@ -2250,7 +2257,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
 hipError_t launch_enumerate(const EnumParams &prm, uint32_t n_blocks, hipStream_t stream)
 {
     if (prm.n_tasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_enumerate, dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
+    if (prm.split_cap != 0) hipLaunchKernelGGL(k_enumerate<true>, dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
+    else hipLaunchKernelGGL(k_enumerate<false>, dim3(n_blocks), dim3(kBlockThreads), 0, stream, prm);
     return hipGetLastError();
 }
 

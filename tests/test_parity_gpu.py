@@ -186,7 +186,9 @@ def test_batch_matches_single(bc):
     # the autotuner's schedule gives the same counts
     tuned = bc.bc_tune_batch(graphs, ps, qs)
     say("tuned", tuned)
-    assert tuned["waves_per_cu"] in (12, 8, 4) and tuned["lds_words"] in (0, 256)
+    # each knob keeps the caller's value (0 = default) unless a candidate ran faster
+    assert tuned["waves_per_cu"] in (0, 12, 8, 4) and tuned["lds_words"] in (0, 256)
+    assert tuned["roots_per_wave"] in (0, 2, 4, 16) and tuned["switch_depth"] in (0, 3, 2)
     vals2, st2 = bc.bc_count_batch(graphs, ps, qs, **tuned)
     assert st2 == st and vals2 == vals
 
