@@ -308,6 +308,28 @@ bc_status bc_scratch_estimate(const bc_graph *g, uint32_t p, uint32_t q, const b
 bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
                         const bc_opts *base, bc_opts *tuned);
 
+/*
+ * bc_count_noalloc -- bc_count for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It calls no hipMalloc, hipFree or other allocating routine:
+ * every scratch buffer of the call (job table, binomial table, result slot,
+ * task queue, candidate counters, bitmap rows, per-wavefront slabs) is carved
+ * from one fixed device array of BC_NOALLOC_SCRATCH_BYTES that the library
+ * keeps on each device it runs on until the process ends.  The caller passes
+ * the graph and receives the count as with bc_count; the grid of the
+ * enumeration shrinks to what the remaining scratch can hold.
+ *
+ * A count whose scratch does not fit fails with BC_E_OOM (bc_last_error says
+ * so) and writes nothing.  opts->alloc must be NULL (BC_E_INVALID_ARG
+ * otherwise); work runs on opts->stream, or on the null stream when it is
+ * NULL, and the call returns once the count is on the host.  All calls on one
+ * device share the array, which keeps the last call's contents (whatever must
+ * start at zero is cleared by each call): calls that overlapped on one device
+ * would race, so the library serialises them with a lock per device.
+ */
+#define BC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+bc_status bc_count_noalloc(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts, bc_u128 *out);
+
 /* Human-readable name of a status code (static storage). */
 const char *bc_status_string(bc_status s);
 

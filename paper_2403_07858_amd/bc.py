@@ -152,6 +152,7 @@ def _load():
         "bc_scratch_estimate": ([P, U32, U32, P, P], I32),
         "bc_partition": ([P, U32, U32, I32, U64, P, P], I32),
         "bc_count_partition": ([P, U32, U32, I32, P, U32, P, P, P], I32),
+        "bc_count_noalloc": ([P, U32, U32, P, P], I32),
         "bc_status_string": ([I32], ctypes.c_char_p),
         "bc_last_error": ([], ctypes.c_char_p),
     }
@@ -165,7 +166,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_htb_stats", "bc_count", "bc_count_roots", "bc_count_batch",
-            "bc_tune_batch", "bc_scratch_estimate", "bc_partition", "bc_count_partition", "bc_status_string", "bc_last_error")
+            "bc_tune_batch", "bc_scratch_estimate", "bc_partition", "bc_count_partition", "bc_count_noalloc", "bc_status_string", "bc_last_error")
 
 
 class BCError(RuntimeError):
@@ -309,6 +310,16 @@ def bc_htb_stats(g: Graph, side: int):
     if s != BC_OK:
         raise BCError(s, "bc_htb_stats")
     return w.value, o.value
+
+
+def bc_count_noalloc(g: Graph, p: int, q: int, **opt):
+    """Exact count with all device scratch in the library's fixed buffer."""
+    o = make_opts(**opt)
+    out = bc_u128()
+    s = _lib.bc_count_noalloc(g.handle, p, q, ctypes.byref(o), ctypes.byref(out))
+    if s != BC_OK:
+        raise BCError(s, "bc_count_noalloc")
+    return out.value
 
 
 def bc_count_roots(g: Graph, p: int, q: int, anchor: int, rank_lo: int, rank_hi: int, with_stats=False, **opt):

@@ -1861,6 +1861,70 @@ extern "C" bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t
 }
 
 // ---------------------------------------------------------------------------
+// bc_count_noalloc: every scratch buffer of the call is carved from this
+// fixed array (one copy per device, held until the process ends).  In host
+// code the array's name is only a stand-in for the device symbol: its device
+// address is looked up once per device and used everywhere instead.
+
+constexpr uint64_t kNoAllocScratchBytes = BC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+
+struct NoAllocDevice {
+    std::mutex mu;           // serialises the calls on one device (they share the array)
+    void *ptr = nullptr;     // device address of `scratch` on this device
+};
+
+NoAllocDevice &noalloc_device(int device)
+{
+    static NoAllocDevice devs[64];
+    return devs[device];
+}
+
+}  // namespace
+
+extern "C" bc_status bc_count_noalloc(const bc_graph *g, uint32_t p, uint32_t q, const bc_opts *opts, bc_u128 *out)
+{
+    g_last_error.clear();
+    if (!g || !out) return set_error(BC_E_INVALID_ARG, "bc_count_noalloc: NULL argument");
+    if (bc_status s = check_pq(p, q)) return s;
+    if (bc_status s = check_opts(opts)) return s;
+    if (BC_OPT(opts, alloc, (const bc_allocator *)nullptr))
+        return set_error(BC_E_INVALID_ARG, "bc_count_noalloc: bc_opts.alloc must be NULL (nothing is allocated)");
+    if (BC_OPT(opts, sets, 0u) != BC_SETS_LOCAL_BITMAP || BC_OPT(opts, bitmap_bits, 0u) != 0)
+        return set_error(BC_E_INVALID_ARG,
+                         "bc_count_noalloc: the global-set path (bc_opts.sets, bitmap_bits) is not available here");
+    if (g->device < 0 || g->device >= 64) return set_error(BC_E_DEVICE, "bc_count_noalloc: device id out of range");
+    NoAllocDevice &dev = noalloc_device(g->device);
+    std::lock_guard<std::mutex> lock(dev.mu);
+    BC_HIP(hipSetDevice(g->device));
+    if (!dev.ptr) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                     "bc_count_noalloc: hipGetSymbolAddress(scratch)");
+        dev.ptr = ptr;
+    }
+    std::vector<JobSpec> sp{JobSpec{g, p, q, opts ? opts->anchor : BC_ANCHOR_AUTO, 0, 0, false, opts_deadline(opts)}};
+    std::vector<bc_u128> res;
+    std::vector<bc_status> ist;
+    bool short_of_room = false;
+    Exec ex;
+    ex.fixed = dev.ptr;
+    ex.fixed_cap = kNoAllocScratchBytes;
+    ex.fixed_short = &short_of_room;
+    bc_status s = run_jobs(sp, opts, res, ist, nullptr, ex);
+    if (short_of_room)
+        return set_error(BC_E_OOM, "bc_count_noalloc: the count needs more device scratch than the fixed " +
+                                       std::to_string(kNoAllocScratchBytes >> 20) + " MiB buffer");
+    if (s != BC_OK) return s;
+    if (ist[0] != BC_OK) return ist[0];
+    *out = res[0];
+    return BC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // BCPar (Algorithm 3, Section VI): roots of one anchor side grouped so that
 // each group's closure -- the roots, their oriented 2-hop candidates and the
 // neighbourhoods of both -- fits a memory budget; each group is then counted
