@@ -132,8 +132,8 @@ typedef struct {
                                   candidate list) or 3 (triples, nodes of <= 96 rows); 0 = auto (3) */
     uint32_t split_rows;       /* runtime split of heavy tasks (p_A >= 5): a (root, second vertex)
                                   task whose level-2 block keeps more rows than this pushes one
-                                  subtask per row to a device queue that idle wavefronts drain;
-                                  0 = auto (256), 0xffffffff = never split */
+                                  subtask per child row to a device queue that idle wavefronts
+                                  drain; 0 or 0xffffffff = never split (the default) */
     uint32_t root_build;       /* BC_ROOT_BUILD_AUTO / _TWO_PASS */
     uint32_t sets;             /* BC_SETS_LOCAL_BITMAP / _HTB / _SORTED (the last two send every root
                                   through the global-set path) */

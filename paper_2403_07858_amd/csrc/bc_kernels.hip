@@ -1809,14 +1809,26 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         return;
     }
 
-    // Level-2 block: rows b > i restricted to S2 and renumbered to S2's bits.
-    uint64_t *blk2 = arena_alloc(ar, (uint64_t)rem * W2, cap_fail);
-    if (!blk2) return;
+    // Level-2 block: rows b > i restricted to S2 and renumbered to S2's bits
+    // (column-major, stride2 words per column).
+    uint64_t *blk2 = nullptr;
+    uint32_t stride2 = rem;
     uint32_t m2 = 0;
     if (nz <= 2 && nz == W2) {
         // Common case: S2 lives in at most two words that need no packing.
         // The two masks stay in registers; the row words of kFilterDepth
-        // chunks are loaded together before any of them is filtered.
+        // chunks are loaded together before any of them is filtered.  A block
+        // too big for the wave's LDS when sized for all rem rows starts there
+        // anyway, with room for as many rows as fit (half the free LDS when
+        // deeper levels follow, so that their blocks keep the other half);
+        // only when more rows than that are kept does it move to a slab
+        // block of rem rows.
+        const uint32_t room = ar.lds_cap - ar.lds_used;
+        uint32_t fit = rem;
+        if (W2 != 0 && (uint64_t)rem * W2 > room) fit = (pA == 4 ? room : room / 2) / W2;
+        stride2 = fit != 0 ? fit : rem;
+        blk2 = arena_alloc(ar, (uint64_t)stride2 * W2, cap_fail);
+        if (!blk2) return;
         glb_u64 *r0 = base + (uint64_t)w0 * k;
         glb_u64 *r1 = base + (uint64_t)(nz > 1 ? w1 : w0) * k;
         for (uint32_t b0 = s + 1; b0 < k; b0 += kFilterDepth * kWaveSize) {
@@ -1834,10 +1846,30 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
                 const uint32_t n = (uint32_t)(__popcll(v0) + __popcll(v1));
                 const bool keep = b < k && n >= q;
                 const uint64_t mask = __ballot(keep);
+                if (m2 + (uint32_t)__popcll(mask) > stride2) {
+                    // the LDS block is full: give its words back and move the
+                    // rows kept so far to a slab block of rem rows
+                    uint64_t *sb = nullptr;
+                    if (ar.holds(blk2) && blk2 + (uint64_t)stride2 * W2 == ar.lds + ar.lds_used) {
+                        ar.lds_used -= stride2 * W2;
+                        sb = arena_alloc(ar, (uint64_t)rem * W2, cap_fail);
+                        if (!sb) return;
+                        for (uint32_t w = 0; w < W2; ++w)
+                            for (uint32_t x = ln; x < m2; x += kWaveSize)
+                                sb[(uint64_t)w * rem + x] = blk2[(uint64_t)w * stride2 + x];
+                        wave_sync();
+                    }
+                    if (!sb) {
+                        *cap_fail = true;   // not reached: the block was the arena's last allocation
+                        return;
+                    }
+                    blk2 = sb;
+                    stride2 = rem;
+                }
                 if (keep) {
                     const uint32_t idx = m2 + mbcnt64(mask);
                     blk2[idx] = v0;
-                    if (nz > 1) blk2[(uint64_t)rem + idx] = v1;
+                    if (nz > 1) blk2[(uint64_t)stride2 + idx] = v1;
                 }
                 m2 += (uint32_t)__popcll(mask);
             }
@@ -1862,6 +1894,10 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
             m2 += (uint32_t)__popcll(mask);
         }
         wave_sync();
+        // the block is sized for the kept rows only
+        stride2 = m2;
+        blk2 = arena_alloc(ar, (uint64_t)m2 * W2, cap_fail);
+        if (!blk2) return;
         for (uint32_t c0 = 0; c0 < m2; c0 += kWaveSize) {
             const uint32_t idx = c0 + ln;
             const bool live = idx < m2;
@@ -1872,7 +1908,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
                 for (uint32_t e = 0; e < nz; ++e) {
                     const uint32_t w = (uint32_t)nzt[8ull * e + 7];
                     const uint64_t x = nzt[8ull * e] & base[(uint64_t)w * k + bb];
-                    if (live) blk2[(uint64_t)e * rem + idx] = x;
+                    if (live) blk2[(uint64_t)e * stride2 + idx] = x;
                 }
             } else {
                 // every lane walks the same entries (uniform control flow)
@@ -1892,19 +1928,19 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
                     const uint32_t cnt = (uint32_t)__popcll(sw);
                     const uint32_t tw = o >> 6, sh = o & 63;
                     while (ow < tw) {
-                        if (live) blk2[(uint64_t)ow * rem + idx] = cur;
+                        if (live) blk2[(uint64_t)ow * stride2 + idx] = cur;
                         cur = 0;
                         ++ow;
                     }
                     cur |= x << sh;
                     if (sh + cnt > 64) {
-                        if (live) blk2[(uint64_t)ow * rem + idx] = cur;
+                        if (live) blk2[(uint64_t)ow * stride2 + idx] = cur;
                         cur = x >> (64 - sh);
                         ++ow;
                     }
                 }
                 while (ow < W2) {
-                    if (live) blk2[(uint64_t)ow * rem + idx] = cur;
+                    if (live) blk2[(uint64_t)ow * stride2 + idx] = cur;
                     cur = 0;
                     ++ow;
                 }
@@ -1939,8 +1975,8 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
             }
             for (uint32_t w = 0; w < W2; ++w)
                 for (uint32_t x = ln; x < m2; x += kWaveSize)
-                    hdr[4 + (uint64_t)w * m2 + x] = ar.holds(blk2) ? blk2[(uint64_t)w * rem + x]
-                                                                   : row_word<false>(blk2, (uint64_t)w * rem + x);
+                    hdr[4 + (uint64_t)w * m2 + x] = ar.holds(blk2) ? blk2[(uint64_t)w * stride2 + x]
+                                                                   : row_word<false>(blk2, (uint64_t)w * stride2 + x);
             // the block must be visible before any entry naming it
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             for (uint32_t x = ln; x < n_sub; x += kWaveSize) ring_put(sp->ring + at + x, off, x);
@@ -1950,7 +1986,7 @@ __device__ void run_task(const Job &jb, uint32_t jidx, const ActiveRoot &rt, uin
         // (a heap block taken without ring room stays unused until the launch ends)
     }
     }
-    dfs_level2(jb, jidx, blk2, rem, m2, W2, s2n, kNoJ, ar, stack, tb, acc, ct, instrument, triple, cap_fail, timed_out,
+    dfs_level2(jb, jidx, blk2, stride2, m2, W2, s2n, kNoJ, ar, stack, tb, acc, ct, instrument, triple, cap_fail, timed_out,
                t0);
 }
 

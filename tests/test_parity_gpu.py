@@ -354,3 +354,34 @@ def test_hubs_per_root(bc, hubs):
         want_run = oracle.count_ranks(g, p, q, list(range(lo, hi)), anchor="U", order_key=oracle.ORDER_DEGREE)
         assert bc.bc_count_roots(G, p, q, 0, lo, hi) == sum(want_run)
         say("hubs per-root", (p, q), len(done), "of", len(ranks))
+
+
+def test_big_deep_per_root_samples(bc, big):
+    # (5,5) and (6,6) per root on U at full size: uniform ranks plus the dense
+    # top of the rank order, under the same oracle budget as above
+    g, G = big
+    n = g.n_u
+    rng_r = gg.draws_u64(78, 1, 0, 64)
+    ranks = sorted({int(x % n) for x in rng_r[:40]} | {int(n - 1 - (x % 400)) for x in rng_r[40:]})
+    for p, q in ((5, 5), (6, 6)):
+        want = oracle.count_ranks(g, p, q, ranks, anchor="U", order_key=oracle.ORDER_DEGREE, max_nodes=3_000_000)
+        done = [(r, w) for r, w in zip(ranks, want) if w is not None]
+        assert len(done) >= 24 and sum(1 for _, w in done if w) >= 5
+        for r, w in done:
+            assert bc.bc_count_roots(G, p, q, 0, r, r + 1) == w, ((p, q), r)
+        say("deep per-root", (p, q), len(done), "of", len(ranks), "compared")
+
+
+def test_big_heavy_roots_run_to_completion(bc, big):
+    # Roots below the densest few thousand, each with 640-1460 candidates of one-
+    # and two-word rows: their early tasks size the level-2 block for every later
+    # candidate, more than a wavefront's LDS arena (896 words) holds, so those
+    # blocks live in the HBM slab.  The oracle runs every root without a budget.
+    g, G = big
+    n = g.n_u
+    ranks = [n - 8000 + 625 * i for i in range(8)]
+    want = oracle.count_ranks(g, 4, 4, ranks, anchor="U", order_key=oracle.ORDER_DEGREE)
+    assert all(w is not None and w > 0 for w in want)
+    for r, w in zip(ranks, want):
+        assert bc.bc_count_roots(G, 4, 4, 0, r, r + 1) == w, r
+    say("heavy roots", list(zip(ranks, want)))
