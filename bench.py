@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--workload", default="power_law_2m", choices=sorted(WORKLOADS))
     ap.add_argument("--queries", default=None, help="e.g. '4,4;4,6'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rank-lo", type=int, default=62000,
+    ap.add_argument("--cpu-rank-lo", type=int, default=61000,
                     help="first U degree rank of the roots the oracle and the device both count at (4,4)")
     ap.add_argument("--cpu-rank-hi", type=int, default=63000)
     ap.add_argument("--sweep", default="6:150,7:20,8:20",
@@ -94,6 +94,10 @@ def main():
     ap.add_argument("--serve-rates", default="10,30,100,300,1000")
     ap.add_argument("--serve-graphs", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=8, help="most queries per served batch")
+    ap.add_argument("--ablation", action="store_true",
+                    help="Section VII ablations (HTB, NB comparator, pure DFS, Border, |N2| order, BCPar)")
+    ap.add_argument("--ablation-cap-s", type=float, default=30.0, help="device time limit per ablation count")
+    ap.add_argument("--border-iters", type=int, default=1024, help="Border swap steps per side (ablation)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -112,6 +116,8 @@ def main():
         return run_serve(args)
     if args.c3:
         return run_c3(args)
+    if args.ablation:
+        return run_ablation(args)
     gen_name, default_q = WORKLOADS[args.workload]
     queries = parse_queries(args.queries) if args.queries else default_q
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
@@ -537,8 +543,18 @@ def run_c3(args):
     done_s = sum(r["seconds"] for r in done)
     sweep = []
     base = None
+    cap_ms = int(args.range_cap_s * 1000)
     for w in [int(x) for x in args.bitmap_sweep.split(",")]:
-        c, st = bc.bc_count(G, 4, 4, anchor=bc.BC_ANCHOR_U, bitmap_bits=w, with_stats=True, stream=stream)
+        try:
+            c, st = bc.bc_count(G, 4, 4, anchor=bc.BC_ANCHOR_U, bitmap_bits=w, with_stats=True, stream=stream,
+                                timeout_ms=cap_ms)
+        except bc.BCError as e:
+            if e.status != bc.BC_E_TIMEOUT:
+                raise
+            sweep.append({"bitmap_bits": w, "status": "capped", "count": None, "ms_total": None,
+                          "ms_enumerate": None})
+            log(f"[c3] (4,4) bitmap_bits {w}: capped at {args.range_cap_s:.0f} s")
+            continue
         ms = []
         for _ in range(2):
             c2, st2 = bc.bc_count(G, 4, 4, anchor=bc.BC_ANCHOR_U, bitmap_bits=w, with_stats=True, stream=stream)
@@ -546,7 +562,8 @@ def run_c3(args):
             ms.append(st2["ms_total"])
         base = c if base is None else base
         assert c == base, "the bitmap width changed a count"
-        sweep.append({"bitmap_bits": w, "count": str(c), "ms_total": min(ms), "ms_enumerate": st2["ms_enumerate"]})
+        sweep.append({"bitmap_bits": w, "status": "done", "count": str(c), "ms_total": min(ms),
+                      "ms_enumerate": st2["ms_enumerate"]})
         log(f"[c3] (4,4) bitmap_bits {w}: {min(ms):.1f} ms")
     line = {
         "metric": "bicliques counted/sec", "value": done_count / done_s if done_s else 0.0, "unit": "bicliques/s",
@@ -557,6 +574,123 @@ def run_c3(args):
                    "range_cap_s": args.range_cap_s},
         "ranges": ranges, "ranges_done": len(done), "ranges_capped": len(ranges) - len(done),
         "bitmap_sweep_44": sweep,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_ablation(args):
+    """Section VII's ablations, each against the default build (degree order,
+    local bitmaps, hybrid DFS-BFS), with every count checked against the
+    default's; a count past the device time limit is reported as capped,
+    not extrapolated.
+    - Whole 2M-edge graph: Border order (Algorithm 2) and the |N_2^q| order
+      key (Definition 2) on the local-bitmap path, with the HTB 1-block
+      counts of both orders (Table III's measure).
+    - A band of roots (ranks [0.61 n, 0.63 n) of the anchor side): the HTB
+      global-set path, the binary-search (NB) comparator on sorted id
+      lists, pure DFS on the global sets (NH), Border + HTB.
+    - BCPar (Algorithm 3) on a 200k-edge graph of the same shape: the groups'
+      counts add up to the whole count; groups, largest closure, time."""
+    import torch
+
+    from paper_2403_07858_amd import bc, graphgen as gg
+
+    log = _log
+    gen_name, _ = WORKLOADS[args.workload]
+    queries = parse_queries(args.queries) if args.queries else [(4, 4), (4, 6), (6, 4)]
+    g = getattr(gg, gen_name)()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cap_ms = int(args.ablation_cap_s * 1000)
+    graphs = {"degree": bc.build_graph(g, stream=stream)}
+    t0 = time.perf_counter()
+    graphs["border"] = bc.build_graph(g, stream=stream, order_key=bc.BC_ORDER_BORDER, border_iters=args.border_iters)
+    border_build_s = time.perf_counter() - t0
+    log(f"[ablation] Border build ({args.border_iters} swap steps per side): {border_build_s:.1f} s")
+    t0 = time.perf_counter()
+    graphs["two_hop"] = bc.build_graph(g, stream=stream, order_key=bc.BC_ORDER_TWO_HOP)
+    two_hop_build_s = time.perf_counter() - t0
+    log(f"[ablation] |N2| order build: {two_hop_build_s:.1f} s")
+    htb = {}
+    for name in ("degree", "border"):
+        for side in (0, 1):
+            words, ones = bc.bc_htb_stats(graphs[name], side)
+            htb[f"{name}_side{side}"] = {"words": words, "one_blocks": ones}
+        log(f"[ablation] {name} order HTB: {htb[name + '_side0']} (U rows) {htb[name + '_side1']} (V rows)")
+
+    def timed(fn, **opt):
+        try:
+            c, st = fn(with_stats=True, stream=stream, timeout_ms=cap_ms, **opt)
+            return c, st["ms_total"], st["ms_enumerate"]
+        except bc.BCError as e:
+            if e.status != bc.BC_E_TIMEOUT:
+                raise
+            return None, None, None
+
+    rows = []
+    for p, q in queries:
+        want, st = bc.bc_count(graphs["degree"], p, q, with_stats=True, stream=stream)
+        anchor = st["anchor"]
+        for name, gname in (("default", "degree"), ("border", "border"), ("two_hop_order", "two_hop")):
+            c, ms, me = timed(lambda **o: bc.bc_count(graphs[gname], p, q, **o))
+            assert c is None or c == want, (name, p, q)
+            rows.append({"scope": "graph", "variant": name, "p": p, "q": q, "status": "done" if c is not None
+                         else "capped", "count": None if c is None else str(c), "ms_total": ms, "ms_enumerate": me})
+            log(f"[ablation] ({p},{q}) whole graph {name}: total {ms} ms, enumeration {me} ms")
+        n = g.n_u if anchor == 0 else g.n_v
+        lo, hi = int(0.61 * n), int(0.63 * n)
+        sub = sub_b = None
+        for name, gname, opt in (("default", "degree", {}), ("htb", "degree", {"sets": bc.BC_SETS_HTB}),
+                                 ("nb_sorted", "degree", {"sets": bc.BC_SETS_SORTED}),
+                                 ("htb_pure_dfs", "degree", {"sets": bc.BC_SETS_HTB, "pure_dfs": True}),
+                                 ("border", "border", {}), ("border_htb", "border", {"sets": bc.BC_SETS_HTB})):
+            c, ms, me = timed(lambda **o: bc.bc_count_roots(graphs[gname], p, q, anchor, lo, hi, **o), **opt)
+            if gname == "degree" and name == "default":
+                sub = c
+            # Border relabels the side, so its band holds other roots: compared among Border runs
+            if name == "border":
+                sub_b = c
+            ref = sub_b if gname == "border" else sub
+            if c is not None and ref is not None:
+                assert c == ref, (name, p, q)
+            rows.append({"scope": f"ranks [{lo},{hi}) of {'UV'[anchor]}", "variant": name, "p": p, "q": q,
+                         "status": "done" if c is not None else "capped", "count": None if c is None else str(c),
+                         "ms_total": ms, "ms_enumerate": me})
+            log(f"[ablation] ({p},{q}) ranks [{lo},{hi}) {name}: total {ms} ms, enumeration {me} ms")
+    # BCPar on a smaller graph of the same shape
+    gs = gg.chung_lu_bipartite(10_000, 5_000, 200_000, 2.1, 2.1, 1000, 1000, seed=5)
+    Gs = bc.build_graph(gs, stream=stream)
+    for p, q in queries:
+        want, st = bc.bc_count(Gs, p, q, with_stats=True, stream=stream)
+        anchor = st["anchor"]
+        whole_ms = st["ms_total"]
+        for budget_kib in (256, 1024):
+            t0 = time.perf_counter()
+            part, n = bc.bc_partition(Gs, p, q, anchor, budget_kib << 10)
+            plan_s = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            tot, biggest = 0, 0
+            for k in range(n):
+                c, edges = bc.bc_count_partition(Gs, p, q, anchor, part, k, stream=stream)
+                tot += c
+                biggest = max(biggest, edges)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            assert tot == want, ("bcpar", p, q)
+            rows.append({"scope": "bcpar graph 10k x 5k, 200k edges", "variant": f"bcpar {budget_kib} KiB",
+                         "p": p, "q": q, "status": "done", "count": str(tot), "groups": n,
+                         "largest_closure_edges": biggest, "partition_s": plan_s, "groups_wall_ms": wall * 1e3,
+                         "whole_count_ms": whole_ms})
+            log(f"[ablation] ({p},{q}) bcpar {budget_kib} KiB: {n} groups (largest closure {biggest} of "
+                f"{gs.n_edges} edges), partition {plan_s:.2f} s, groups {wall * 1e3:.1f} ms, whole {whole_ms:.1f} ms")
+    line = {
+        "metric": "bicliques counted/sec", "value": None, "unit": "bicliques/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "u128", "data": "synthetic",
+        "config": {"workload": args.workload, "queries": [f"({p},{q})" for p, q in queries],
+                   "n_u": g.n_u, "n_v": g.n_v, "edges": g.n_edges, "sha256": g.manifest["sha256"],
+                   "cap_s": args.ablation_cap_s, "border_iters": args.border_iters},
+        "build_s": {"border": border_build_s, "two_hop": two_hop_build_s},
+        "htb": htb, "ablation": rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -26,7 +26,8 @@
 
 namespace bcdev {
 
-constexpr uint32_t kLdsWordsPerWave = 1024;   // LDS arena per wavefront (64-bit words): 3 blocks of 4 waves fill 160 KiB
+constexpr uint32_t kLdsWordsPerWave = 960;    // LDS arena per wavefront (64-bit words): with the spread table,
+                                              // 3 blocks of 4 waves fill 160 KiB
 constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of the tiled leaf sum
 constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
@@ -1174,9 +1175,11 @@ __device__ void pair_sum_tile(const uint64_t *blk, uint32_t stride, uint32_t m, 
 // 64-bit row word).  Operand layout: lane l holds row (l mod 16) of a 16-row
 // block, bits [16 (l / 16), 16 (l / 16) + 16) of each word spread to one byte
 // per bit; the A and B operands of a block are built the same way, so every
-// bit position meets its partner.  The B side is spread as 0/4 bytes and the
-// accumulator starts at the LDS byte address of the C(n, q) table, so each
-// result is already the address of its leaf value.  Result register i of
+// bit position meets its partner.  One operand is spread as 0/4 bytes (the
+// one built once per column group or pair block) and the other, streamed
+// one, as 0/1 bytes through a table; the accumulator starts at the LDS byte
+// address of the C(n, q) table, so each result is already the address of its
+// leaf value.  Result register i of
 // lane l is entry (4 (l / 16) + i, l mod 16) of the block; in a diagonal
 // block only entries above the diagonal count.  Rows past m are zero and add
 // C(0, q) = 0.
@@ -1218,6 +1221,36 @@ __device__ __forceinline__ v4i mfma_block(const v4i (&ei)[W], const v4i (&ej)[W]
 typedef __attribute__((address_space(1))) const uint64_t glb_u64;
 typedef __attribute__((address_space(3))) const uint64_t lds_u64;
 
+// Eight-bit spreads for the matrix-core operands, one table per block
+// (k_enumerate fills it before its first task): entry v holds bit k of v in
+// byte k, as 0 or 1.
+__shared__ uint64_t spread_lut[256];
+
+__device__ __forceinline__ uint64_t spread_lut_entry(uint32_t v)
+{
+    uint64_t e = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e |= (uint64_t)((v >> k) & 1u) << (8 * k);
+    return e;
+}
+
+// spread_bits<1> through the table: bits [sh, sh + 16) of x (sh = 16 (lane /
+// 16)) as 16 bytes of value 0 or 1, in two LDS reads instead of twelve ALU
+// operations.
+__device__ __forceinline__ v4i spread1_lut(uint64_t x, uint32_t sh)
+{
+    const uint32_t c = (uint32_t)(x >> sh);
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_u64 *)spread_lut;
+    const uint64_t lo = *(lds_u64 *)(uintptr_t)(base + ((c & 0xffu) << 3));
+    const uint64_t hi = *(lds_u64 *)(uintptr_t)(base + (((c >> 8) & 0xffu) << 3));
+    v4i e;
+    e[0] = (int)(uint32_t)lo;
+    e[1] = (int)(uint32_t)(lo >> 32);
+    e[2] = (int)(uint32_t)hi;
+    e[3] = (int)(uint32_t)(hi >> 32);
+    return e;
+}
+
 // Rows in LDS or in the wave's slab: typed loads, so that row fetches from
 // the slab count only against vmcnt and the leaf-table reads' lgkmcnt waits
 // do not wait for them.
@@ -1234,6 +1267,7 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
     const uint32_t ln = lane_id();
     const uint32_t r16 = ln & 15;
     const uint32_t nb = (m + 15) >> 4;
+    const uint32_t sh = 16 * (ln >> 4);
     const int tb = (int)lds_addr(t32);   // t32[0] = C(0, q) = 0
     const v4i c0 = {tb, tb, tb, tb};
     bool above[4];
@@ -1268,7 +1302,7 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
         for (uint32_t I = 0; I < J0; ++I) {
             v4i ei[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) ei[w] = spread_bits<1>(nx[w], ln);
+            for (int w = 0; w < W; ++w) ei[w] = spread1_lut(nx[w], sh);
             fetch(I + 1, nx);
             v4i d[G];
 #pragma unroll
@@ -1284,7 +1318,7 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
         for (uint32_t I = J0; I < imax; ++I) {
             v4i ei[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) ei[w] = spread_bits<1>(nx[w], ln);
+            for (int w = 0; w < W; ++w) ei[w] = spread1_lut(nx[w], sh);
             if (I + 1 < imax) fetch(I + 1, nx);
             uint32_t s = 0;
 #pragma unroll
@@ -1417,6 +1451,7 @@ __device__ void triple_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m
     wave_sync();
     // 2. pair-row blocks against row blocks c > b
     const uint32_t nbc = (m + 15) >> 4;
+    const uint32_t sh = 16 * (ln >> 4);
     const int tb = (int)lds_addr(t32);   // t32[0] = C(0, q) = 0
     const v4i c0 = {tb, tb, tb, tb};
     for (uint32_t i0 = 0; i0 < np; i0 += 16) {
@@ -1425,7 +1460,7 @@ __device__ void triple_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m
         const uint32_t prr = pv ? pr : np - 1;
         v4i ea[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) ea[w] = spread_bits<1>(pv ? P[(uint64_t)w * pcap + prr] : 0ull, ln);
+        for (int w = 0; w < W; ++w) ea[w] = spread_bits<4>(pv ? P[(uint64_t)w * pcap + prr] : 0ull, ln);
         const uint32_t bmine = pv ? Pb[prr] : 0xffffffffu;
         uint32_t brow[4];
 #pragma unroll
@@ -1439,7 +1474,7 @@ __device__ void triple_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const uint64_t x = row_word<Lds>(blk, (uint64_t)w * stride + cc);
-                eb[w] = spread_bits<4>(c < m ? x : 0ull, ln);
+                eb[w] = spread1_lut(c < m ? x : 0ull, sh);
             }
             const v4i dd = mfma_block<W>(ea, eb, c0);
             uint32_t s = 0;
@@ -1464,6 +1499,7 @@ __device__ void pair_row_block_mfma(const uint64_t *blk, uint32_t stride, uint32
     const uint32_t ln = lane_id();
     const uint32_t r16 = ln & 15;
     const uint32_t nb = (m + 15) >> 4;
+    const uint32_t sh = 16 * (ln >> 4);
     const int tb = (int)lds_addr(t32);
     const v4i c0 = {tb, tb, tb, tb};
     auto fetch = [&](uint32_t B, uint64_t (&x)[W]) {
@@ -1479,14 +1515,14 @@ __device__ void pair_row_block_mfma(const uint64_t *blk, uint32_t stride, uint32
     fetch(I, x);
     v4i ea[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) ea[w] = spread_bits<1>(x[w], ln);
+    for (int w = 0; w < W; ++w) ea[w] = spread_bits<4>(x[w], ln);
     uint64_t s64 = 0;
     uint64_t nx[W];
     fetch(I, nx);
     for (uint32_t J = I; J < nb; ++J) {
         v4i eb[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) eb[w] = spread_bits<4>(nx[w], ln);
+        for (int w = 0; w < W; ++w) eb[w] = spread1_lut(nx[w], sh);
         fetch(J + 1, nx);
         const v4i d = mfma_block<W>(ea, eb, c0);
         uint32_t s = 0;
@@ -2138,6 +2174,9 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     __shared__ uint64_t tiles[kWavesPerBlock][kWaveSize * kTileWords];
     const uint32_t wv = threadIdx.x / kWaveSize, ln = lane_id();
     const uint64_t wave_global = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    static_assert(kBlockThreads == 256, "one spread-table entry per thread");
+    spread_lut[threadIdx.x] = spread_lut_entry(threadIdx.x);
+    __syncthreads();
     uint64_t *stack = &lds[wv][0];
     Arena arena;
     arena.lds = &lds[wv][kStackWords];
