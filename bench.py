@@ -40,9 +40,9 @@ HBM_PEAK = 8.0e12
 # HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
 # 1 GiB device copy), valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256_PREFIX = "95d1750a23bec4b4"
+TRAFFIC_KERNEL_SHA256_PREFIX = "521f6ae297197202"
 TRAFFIC_WORKLOAD = "power_law_2m"
-TRAFFIC_BYTES_Q44 = (1156403.0625 * 2.0 + 6162921.90625 * 1.0) * 1024
+TRAFFIC_BYTES_Q44 = (922980.125 * 2.0 + 1033624.75 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4), (5, 5)]),
@@ -357,6 +357,7 @@ def capped_sweep(G, stream, spec, log):
         pq, cap = part.split(":")
         k = int(pq)
         cap_s = float(cap)
+        log(f"[bench] sweep ({k},{k}) under a {cap_s:.0f} s device time limit")
         t0 = time.perf_counter()
         try:
             c, st = bc.bc_count(G, k, k, with_stats=True, stream=stream, timeout_ms=int(cap_s * 1000))
