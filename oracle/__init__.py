@@ -55,9 +55,10 @@ def _load():
         lib.oracle_htb_encode.argtypes = [P, U32, U32, P, P, P]
         lib.oracle_htb_intersect.argtypes = [P, P, U32, P, P, U32, P, P, P]
         lib.oracle_binom.argtypes = [U32, U32, P, P]
+        lib.oracle_count_per_vertex.argtypes = [U64, U64, P, P, U32, U32, P, P, P, P]
         for f in (lib.oracle_count, lib.oracle_count_ranks, lib.oracle_order,
                   lib.oracle_basic_sets, lib.oracle_htb_encode, lib.oracle_htb_intersect,
-                  lib.oracle_binom):
+                  lib.oracle_binom, lib.oracle_count_per_vertex):
             f.restype = I
         _lib = lib
     return _lib
@@ -104,6 +105,23 @@ def count(g, p, q, *, anchor="U", **kw):
     if anchor == "U":
         return count_csr(g.n_u, g.n_v, g.indptr_u, g.indices_u, p, q, **kw)
     return count_csr(g.n_v, g.n_u, g.indptr_v, g.indices_v, q, p, **kw)
+
+
+def count_per_vertex(g, p, q):
+    """Per-vertex counts (python ints): ([bicliques holding x in L for x in U],
+    [bicliques holding v in R for v in V]).  Single-threaded; small graphs."""
+    lib = _load()
+    ip, ix = _csr(g.indptr_u, g.indices_u)
+    ul = np.zeros(max(1, g.n_u), dtype=np.uint64)
+    uh = np.zeros(max(1, g.n_u), dtype=np.uint64)
+    vl = np.zeros(max(1, g.n_v), dtype=np.uint64)
+    vh = np.zeros(max(1, g.n_v), dtype=np.uint64)
+    rc = lib.oracle_count_per_vertex(g.n_u, g.n_v, _ptr(ip), _ptr(ix), p, q, _ptr(ul), _ptr(uh), _ptr(vl),
+                                     _ptr(vh))
+    if rc != OK:
+        raise OracleError(rc, "count_per_vertex")
+    return ([(int(h) << 64) | int(l) for l, h in zip(ul[:g.n_u], uh[:g.n_u])],
+            [(int(h) << 64) | int(l) for l, h in zip(vl[:g.n_v], vh[:g.n_v])])
 
 
 def count_ranks(g, p, q, ranks, *, anchor="U", order_key=ORDER_DEGREE, threads=None, max_nodes=0):

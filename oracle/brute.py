@@ -26,3 +26,17 @@ def count_pairs(n_u, n_v, adj, p, q):
 
 def count_graph(g, p, q):
     return count_pairs(g.n_u, g.n_v, adjacency_sets(g.n_u, g.indptr_u, g.indices_u), p, q)
+
+
+def per_vertex_pairs(n_u, n_v, adj, p, q):
+    """For every x in U and v in V, how many (L, R) with |L| = p, |R| = q and
+    L x R within E hold x in L (resp. v in R), by testing every pair of subsets."""
+    cu, cv = [0] * n_u, [0] * n_v
+    for L in combinations(range(n_u), p):
+        for R in combinations(range(n_v), q):
+            if all(v in adj[u] for u in L for v in R):
+                for x in L:
+                    cu[x] += 1
+                for v in R:
+                    cv[v] += 1
+    return cu, cv

@@ -36,6 +36,12 @@
  *
  * Counts are exact unsigned 128-bit integers; every addition is checked and
  * an overflow is reported as an error, never wrapped.
+ *
+ * Per-vertex counts (oracle_count_per_vertex) reduce the output set of
+ * Algorithm 1 to membership counts: how many bicliques hold each x in U (in
+ * L) and each v in V (in R).  They come from the same leaf rule, visiting
+ * every p-subset L once by increasing ids: L's C(n, q) bicliques all hold
+ * each member of L, and C(n-1, q-1) of them hold a given common neighbour.
  */
 #include <pthread.h>
 #include <stdatomic.h>
@@ -711,4 +717,111 @@ int oracle_htb_intersect(const uint64_t *idx_a, const uint64_t *val_a, uint32_t 
     }
     *n_out = m;
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Per-vertex counts: the output set of Algorithm 1 reduced to how many
+ * bicliques each vertex belongs to.                                   */
+
+typedef struct {
+    const og_graph *g;
+    const binom_table *bt;
+    uint32_t p, q;
+    uint32_t *L;       /* L[0 .. depth): members chosen so far, increasing ids */
+    uint32_t **S;      /* S[d]: common neighbours of L[0 .. d) */
+    uint32_t *nS;      /* |S[d]| */
+    u128 *cu, *cv;     /* per-vertex totals of U and V */
+} pv_t;
+
+/* Extends L (depth members, S = S[depth]) by every x > the last member.  A
+ * complete L with n = |S| common neighbours holds C(n, q) bicliques (any q of
+ * S as R): each member of L is in all of them, and each v in S is in the
+ * C(n-1, q-1) of them whose R contains v.  A subset whose S has fewer than q
+ * vertices holds none and neither does any subset that extends it, so it is
+ * not extended. */
+static int pv_extend(pv_t *w, uint32_t depth, uint32_t from)
+{
+    const og_graph *g = w->g;
+    for (uint64_t x = from; x < g->n_u; ++x) {
+        const uint32_t *Nx = g->adj_u + g->ptr_u[x];
+        const uint32_t dx = (uint32_t)(g->ptr_u[x + 1] - g->ptr_u[x]);
+        uint32_t n;
+        if (depth == 0) {
+            memcpy(w->S[1], Nx, dx * sizeof(uint32_t));
+            n = dx;
+        } else {
+            n = merge_intersect(w->S[depth], w->nS[depth], Nx, dx, w->S[depth + 1]);
+        }
+        if (n < w->q) continue;
+        w->nS[depth + 1] = n;
+        w->L[depth] = (uint32_t)x;
+        if (depth + 1 == w->p) {
+            u128 all = 0, with_v = 0;
+            int rc = binom_get(w->bt, n, w->q, &all);
+            if (rc == OR_OK) rc = binom_get(w->bt, n - 1, w->q - 1, &with_v);
+            if (rc != OR_OK) return rc;
+            for (uint32_t i = 0; i < w->p; ++i)
+                if (add_u128(&w->cu[w->L[i]], all) != OR_OK) return OR_E_OVERFLOW;
+            for (uint32_t i = 0; i < n; ++i)
+                if (add_u128(&w->cv[w->S[depth + 1][i]], with_v) != OR_OK) return OR_E_OVERFLOW;
+        } else {
+            int rc = pv_extend(w, depth + 1, (uint32_t)x + 1);
+            if (rc != OR_OK) return rc;
+        }
+    }
+    return OR_OK;
+}
+
+/*
+ * Per-vertex counts: for every x in U, the number of (p,q)-bicliques (L, R)
+ * with x in L, into (u_lo[x], u_hi[x]); for every v in V, the number with v in
+ * R, into (v_lo[v], v_hi[v]).  Single-threaded, for small graphs.
+ */
+int oracle_count_per_vertex(uint64_t n_u, uint64_t n_v, const uint64_t *indptr_u, const uint32_t *indices_u,
+                            uint32_t p, uint32_t q, uint64_t *u_lo, uint64_t *u_hi, uint64_t *v_lo,
+                            uint64_t *v_hi)
+{
+    if (!u_lo || !u_hi || !v_lo || !v_hi || p == 0 || q == 0 || p > 256 || q > 256) return OR_E_ARG;
+    og_graph g;
+    int rc = graph_load(&g, n_u, n_v, indptr_u, indices_u);
+    if (rc != OR_OK) return rc;
+    binom_table bt = {0};
+    pv_t w;
+    memset(&w, 0, sizeof(w));
+    w.g = &g;
+    w.bt = &bt;
+    w.p = p;
+    w.q = q;
+    w.L = (uint32_t *)calloc(p + 1, sizeof(uint32_t));
+    w.S = (uint32_t **)calloc(p + 2, sizeof(uint32_t *));
+    w.nS = (uint32_t *)calloc(p + 2, sizeof(uint32_t));
+    w.cu = (u128 *)calloc(n_u ? n_u : 1, sizeof(u128));
+    w.cv = (u128 *)calloc(n_v ? n_v : 1, sizeof(u128));
+    if (!w.L || !w.S || !w.nS || !w.cu || !w.cv) rc = OR_E_OOM;
+    for (uint32_t d = 0; rc == OR_OK && d <= p + 1; ++d) {
+        w.S[d] = (uint32_t *)malloc((g.max_deg_u + 1) * sizeof(uint32_t));
+        if (!w.S[d]) rc = OR_E_OOM;
+    }
+    if (rc == OR_OK) rc = binom_init(&bt, g.max_deg_u, q);
+    if (rc == OR_OK) rc = pv_extend(&w, 0, 0);
+    if (rc == OR_OK) {
+        for (uint64_t x = 0; x < n_u; ++x) {
+            u_lo[x] = (uint64_t)w.cu[x];
+            u_hi[x] = (uint64_t)(w.cu[x] >> 64);
+        }
+        for (uint64_t v = 0; v < n_v; ++v) {
+            v_lo[v] = (uint64_t)w.cv[v];
+            v_hi[v] = (uint64_t)(w.cv[v] >> 64);
+        }
+    }
+    if (w.S)
+        for (uint32_t d = 0; d <= p + 1; ++d) free(w.S[d]);
+    free(w.S);
+    free(w.nS);
+    free(w.L);
+    free(w.cu);
+    free(w.cv);
+    binom_free(&bt);
+    graph_free(&g);
+    return rc;
 }

@@ -319,3 +319,41 @@ def test_per_root_values_by_brute_force(oracle_lib, seed):
         want = _per_root_brute(adj, n, pa, qa, key=lambda x: (size[x], x))
         got = oracle_lib.count_ranks(g, p, q, list(range(n)), anchor=anchor, order_key=oracle_lib.ORDER_TWO_HOP)
         assert got == [want[by_two_hop[r]] for r in range(n)], (anchor, "two-hop")
+
+
+# --------------------------------------------------------------------------
+# Per-vertex counts (the output set of Algorithm 1 as membership counts).
+
+@pytest.mark.parametrize("seed", range(4))
+def test_per_vertex_by_brute_force(oracle_lib, seed):
+    g = _random_graph(6 + seed % 3, 7, 0.45 + 0.05 * seed, 300 + seed)
+    adj = brute.adjacency_sets(g.n_u, g.indptr_u, g.indices_u)
+    for p in range(1, 4):
+        for q in range(1, 4):
+            want_u, want_v = brute.per_vertex_pairs(g.n_u, g.n_v, adj, p, q)
+            got_u, got_v = oracle_lib.count_per_vertex(g, p, q)
+            assert (got_u, got_v) == (want_u, want_v), (p, q)
+
+
+@pytest.mark.parametrize("a,b", [(3, 4), (5, 2), (6, 6)])
+def test_per_vertex_complete_bipartite(oracle_lib, a, b):
+    # in K_{a,b} every vertex of a side is alike: x in U is in C(a-1, p-1) C(b, q)
+    # bicliques, v in V in C(a, p) C(b-1, q-1)
+    g = _complete(a, b)
+    for p, q in [(1, 1), (2, 2), (2, 3), (3, 2)]:
+        cu, cv = oracle_lib.count_per_vertex(g, p, q)
+        assert cu == [math.comb(a - 1, p - 1) * math.comb(b, q)] * a
+        assert cv == [math.comb(a, p) * math.comb(b - 1, q - 1)] * b
+
+
+def test_per_vertex_sums_and_side_swap(oracle_lib):
+    # every biclique has p members in L and q in R; swapping the sides swaps the lists
+    g = gg.small_er()
+    gt = gg.graph_from_pairs(g.n_v, g.n_u, g.indices_u.astype(np.int64),
+                             np.repeat(np.arange(g.n_u), np.diff(g.indptr_u).astype(np.int64)))
+    for p, q in [(2, 2), (3, 2), (2, 4)]:
+        cu, cv = oracle_lib.count_per_vertex(g, p, q)
+        total = oracle_lib.count(g, p, q)
+        assert sum(cu) == p * total and sum(cv) == q * total
+        tu, tv = oracle_lib.count_per_vertex(gt, q, p)
+        assert (tu, tv) == (cv, cu)
