@@ -46,8 +46,8 @@ TRAFFIC_BYTES_Q44 = (922980.125 * 2.0 + 1033624.75 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4), (5, 5)]),
-    # 1M x 400k, 20M edges: (6,6) does not finish on it (see the design notes);
-    # these are the queries that do
+    # 1M x 400k, 20M edges: the timed step; (6,6) runs in root ranges under
+    # --c3
     "power_law_20m": ("power_law_20m", [(3, 3), (4, 4), (5, 5)]),
     "small_er": ("small_er", [(3, 3)]),
 }
@@ -103,7 +103,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(the count is additive over root ranges; see the design notes)", file=sys.stderr)
+              "(the count is additive over root ranges, so each GPU could take its own ranges)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -253,6 +253,24 @@ bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const
                          size_t n, const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st);
 
 /*
+ * bc_count_per_vertex -- per-vertex counts (the output set B of Algorithm 1
+ * reduced to how many bicliques each vertex belongs to): for
+ * every vertex x of `side` (BC_ANCHOR_U or BC_ANCHOR_V), the number of
+ * (p,q)-bicliques (L, R), L in U with |L| = p and R in V with |R| = q, that
+ * hold x (in L for side U, in R for side V).  counts (host, one entry per
+ * vertex of that side, indexed by the caller's vertex id) receives them;
+ * their sum is p (side U) or q (side V) times bc_count.  The search runs with
+ * `side` as the anchor on the global-set path, which visits every leaf with
+ * its members known: a leaf's C(n, q_A) bicliques are added to each of its
+ * p_A members (p_A = 1 is the closed form C(d(x), q_A)).  opts->sets picks
+ * HTB (default) or sorted lists; pure_dfs is ignored.  Device scratch of 16
+ * bytes per vertex of the side comes on top of the count's.  Errors as for
+ * bc_count; on error counts is untouched.
+ */
+bc_status bc_count_per_vertex(const bc_graph *g, uint32_t p, uint32_t q, int32_t side, const bc_opts *opts,
+                              bc_u128 *counts);
+
+/*
  * bc_partition -- BCPar (Algorithm 3, Section VI): groups the roots of one
  * anchor side (BC_ANCHOR_U or _V; the anchor's depth, p for U and q for V,
  * must be at least 3) so that each group's closure -- its roots, their
@@ -300,10 +318,13 @@ bc_status bc_scratch_estimate(const bc_graph *g, uint32_t p, uint32_t q, const b
  * with the shortest sample time (coordinate descent, after one warm-up run):
  * waves_per_cu (12, 8, 4), lds_words (default, 256), roots_per_wave (auto,
  * 2, 4, 16), switch_depth (3, 2) and, when a sampled item has min(p, q) >= 5,
- * split_rows (default, 64, 256, 1024).  *tuned receives base (NULL =
- * defaults) with the chosen values.  No count depends on these options.  A
- * sample item that fails (e.g. over base's time limit) counts as taking the
- * whole limit.  Returns argument or device errors.
+ * split_rows (default, 64, 256, 1024).  When the choice differs from base,
+ * both are then timed once over all n items and the faster is kept (a
+ * sample has fewer tasks per wavefront than the whole batch, so a schedule
+ * can win on the sample and lose on the batch).  *tuned receives base (NULL
+ * = defaults) with the chosen values.  No count depends on these options.
+ * A sample item that fails (e.g. over base's time limit) counts as taking
+ * the whole limit.  Returns argument or device errors.
  */
 bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
                         const bc_opts *base, bc_opts *tuned);

@@ -153,6 +153,7 @@ def _load():
         "bc_partition": ([P, U32, U32, I32, U64, P, P], I32),
         "bc_count_partition": ([P, U32, U32, I32, P, U32, P, P, P], I32),
         "bc_count_noalloc": ([P, U32, U32, P, P], I32),
+        "bc_count_per_vertex": ([P, U32, U32, I32, P, P], I32),
         "bc_status_string": ([I32], ctypes.c_char_p),
         "bc_last_error": ([], ctypes.c_char_p),
     }
@@ -166,7 +167,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("bc_build", "bc_free", "bc_graph_info", "bc_ranks", "bc_htb_stats", "bc_count", "bc_count_roots", "bc_count_batch",
-            "bc_tune_batch", "bc_scratch_estimate", "bc_partition", "bc_count_partition", "bc_count_noalloc", "bc_status_string", "bc_last_error")
+            "bc_tune_batch", "bc_scratch_estimate", "bc_partition", "bc_count_partition", "bc_count_noalloc", "bc_count_per_vertex", "bc_status_string",
+            "bc_last_error")
 
 
 class BCError(RuntimeError):
@@ -320,6 +322,18 @@ def bc_count_noalloc(g: Graph, p: int, q: int, **opt):
     if s != BC_OK:
         raise BCError(s, "bc_count_noalloc")
     return out.value
+
+
+def bc_count_per_vertex(g: Graph, p: int, q: int, side: int, **opt):
+    """Per-vertex counts (python ints) for the vertices of `side`, by vertex id:
+    the (p,q)-bicliques holding each vertex."""
+    n = g.n_u if side == BC_ANCHOR_U else g.n_v
+    o = make_opts(**opt)
+    out = (bc_u128 * max(1, n))()
+    s = _lib.bc_count_per_vertex(g.handle, p, q, side, ctypes.byref(o), out)
+    if s != BC_OK:
+        raise BCError(s, "bc_count_per_vertex")
+    return [out[i].value for i in range(n)]
 
 
 def bc_count_roots(g: Graph, p: int, q: int, anchor: int, rank_lo: int, rank_hi: int, with_stats=False, **opt):

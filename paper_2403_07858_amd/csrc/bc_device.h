@@ -35,6 +35,10 @@ struct Job {
     const uint64_t *htb_off;
     const uint32_t *htb_idx;
     const uint32_t *htb_val;
+    // per-vertex counts of side A (two 64-bit words per vertex, by rank): the
+    // bicliques each vertex is an L member of; NULL when not asked for (only
+    // the global-set path fills them)
+    uint64_t *pv;
 };
 
 // One root of the global-set path (set intersections over the graph's own

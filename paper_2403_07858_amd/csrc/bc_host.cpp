@@ -212,7 +212,9 @@ std::vector<uint32_t> border_order(uint64_t n, const std::vector<uint32_t> &orde
                                    const uint64_t *ptr_o, const std::vector<uint32_t> &rows_o,
                                    const uint64_t *ptr_x, const std::vector<uint32_t> &cols_x, uint64_t iters)
 {
-    constexpr uint32_t kCand = 64;   // candidates whose profit is evaluated per step (see the design notes)
+    // candidates whose profit is evaluated per step: all of the least-overlap
+    // vertices would cost O(|V| d) per swap; the 64 in the most 1-blocks stand for them
+    constexpr uint32_t kCand = 64;
     std::vector<uint32_t> xat(order), pos(n);
     for (uint64_t i = 0; i < n; ++i) pos[xat[i]] = (uint32_t)i;
     // per row: occupied blocks and how many of its members each holds
@@ -732,6 +734,7 @@ struct JobSpec {
     bool ranged;
     uint64_t deadline_ns;      // steady clock, 0 = none
     const std::vector<uint8_t> *root_mask = nullptr;   // p_A >= 3 only: roots (by rank) that get tasks
+    bc_u128 *pv_out = nullptr;   // per-vertex counts of the anchor side, by rank (explicit anchor, p_A >= 2)
 };
 
 // Device real-time clock against the host steady clock, per device.  The
@@ -1084,6 +1087,17 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         }
         tab_off[j + 1] = tab_off[j] + cols[j].size();
     }
+    // per-vertex counters (two 64-bit words per vertex of the anchor side)
+    bool any_pv = false;
+    std::vector<uint64_t *> d_pv(nj, nullptr);
+    for (uint32_t j = 0; j < nj; ++j) {
+        if (!specs[jobs[j].spec].pv_out) continue;
+        any_pv = true;
+        const uint64_t n = specs[jobs[j].spec].g->side[jobs[j].anchor].n;
+        BC_HIP(mem.get(&d_pv[j], 2 * std::max<uint64_t>(n, 1)));
+        BC_HIP(fill_u32((uint32_t *)d_pv[j], 4 * std::max<uint64_t>(n, 1), 0u, st));
+        hjobs[j].pv = d_pv[j];
+    }
     bcdev::Job *d_jobs;
     u128 *d_tab;
     bcdev::Slot *d_slots;
@@ -1360,7 +1374,9 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         const std::vector<uint8_t> *mask = specs[hj.spec].root_mask;
         for (uint64_t r = root_prefix[c]; r < root_prefix[c + 1]; ++r) {
             cand_edges += h_k[r];
-            if (hj.pA < 3 || h_k[r] < hj.pA - 1) continue;
+            // per-vertex counts also take the p_A = 2 roots through the
+            // global-set path (the candidate pass sums their leaves unattributed)
+            if (hj.pA < (specs[hj.spec].pv_out ? 2u : 3u) || h_k[r] < hj.pA - 1) continue;
             uint32_t u = (uint32_t)(hj.root_lo + (r - root_prefix[c]));
             if (mask && !(*mask)[u]) continue;
             uint32_t w1 = (uint32_t)((A.h_ptr[u + 1] - A.h_ptr[u] + 63) / 64);
@@ -1388,16 +1404,19 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
     }
     // Roots of the global-set path: all of them with sets = HTB or SORTED;
     // with local bitmaps, those with more neighbours than bitmap_bits (they
-    // take HTB).  They keep their place in the cost order.
+    // take HTB).  Jobs with per-vertex counts send all their roots there: it
+    // visits every leaf with its members known.  They keep their place in
+    // the cost order.
     std::vector<Plan> splan;
     const uint32_t set_mode = sets_opt == BC_SETS_SORTED ? bcdev::SETS_SORTED : bcdev::SETS_HTB;
-    if (sets_opt != BC_SETS_LOCAL_BITMAP || bitmap_bits) {
+    if (sets_opt != BC_SETS_LOCAL_BITMAP || bitmap_bits || any_pv) {
         std::vector<Plan> keep;
         for (const Plan &pl : plan) {
             const HostJob &hj = jobs[cj[pl.c]];
             const Side &A = specs[hj.spec].g->side[hj.anchor];
             const uint64_t du = A.h_ptr[pl.root + 1] - A.h_ptr[pl.root];
-            const bool to_sets = sets_opt != BC_SETS_LOCAL_BITMAP || du > bitmap_bits;
+            const bool to_sets = sets_opt != BC_SETS_LOCAL_BITMAP || (bitmap_bits && du > bitmap_bits) ||
+                                 specs[hj.spec].pv_out != nullptr;
             (to_sets ? splan : keep).push_back(pl);
         }
         plan.swap(keep);
@@ -1582,7 +1601,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         sp.ids = d_ids;
         sp.mode = set_mode;
         sp.instrument = instrument ? 1u : 0u;
-        sp.pure_dfs = BC_OPT(opts, pure_dfs, 0u) ? 1u : 0u;
+        sp.pure_dfs = (BC_OPT(opts, pure_dfs, 0u) && !any_pv) ? 1u : 0u;   // per-vertex needs the hybrid
         sp.slab = d_sslab;
         sp.slab_words = set_slab_need;
         sp.queue = d_queue + 9;
@@ -1593,8 +1612,18 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
     tm.mark(4, st);
     std::vector<bcdev::Slot> hs(nj);
     BC_HIP(hipMemcpyAsync(hs.data(), d_slots, nj * sizeof(bcdev::Slot), hipMemcpyDeviceToHost, st));
+    std::vector<std::vector<uint64_t>> h_pv(nj);
+    for (uint32_t j = 0; j < nj; ++j) {
+        if (!d_pv[j]) continue;
+        h_pv[j].resize(2 * specs[jobs[j].spec].g->side[jobs[j].anchor].n);
+        if (!h_pv[j].empty())
+            BC_HIP(hipMemcpyAsync(h_pv[j].data(), d_pv[j], h_pv[j].size() * 8, hipMemcpyDeviceToHost, st));
+    }
     BC_HIP(hipStreamSynchronize(st));
     read_back = true;
+    for (uint32_t j = 0; j < nj; ++j)
+        for (size_t r = 0; 2 * r < h_pv[j].size(); ++r)
+            specs[jobs[j].spec].pv_out[r] = bc_u128{h_pv[j][2 * r], h_pv[j][2 * r + 1]};
     if (short_first) {
         // learn from a served batch that enumerated exactly one job to the end
         int only = -1, live = 0;
@@ -1738,6 +1767,41 @@ extern "C" bc_status bc_count_roots(const bc_graph *g, uint32_t p, uint32_t q, i
     return BC_OK;
 }
 
+extern "C" bc_status bc_count_per_vertex(const bc_graph *g, uint32_t p, uint32_t q, int32_t side, const bc_opts *opts,
+                                         bc_u128 *counts)
+{
+    g_last_error.clear();
+    if (!g || !counts) return set_error(BC_E_INVALID_ARG, "bc_count_per_vertex: NULL argument");
+    if (bc_status s = check_pq(p, q)) return s;
+    if (bc_status s = check_opts(opts)) return s;
+    if (side != BC_ANCHOR_U && side != BC_ANCHOR_V)
+        return set_error(BC_E_INVALID_ARG, "bc_count_per_vertex: side must be BC_ANCHOR_U or BC_ANCHOR_V");
+    const Side &A = g->side[side];
+    const uint32_t pA = side == BC_ANCHOR_U ? p : q, qA = side == BC_ANCHOR_U ? q : p;
+    std::vector<bc_u128> by_rank(A.n, bc_u128{0, 0});
+    if (pA == 1) {
+        // each vertex x is the whole L of C(d(x), q_A) bicliques
+        std::vector<u128> col;
+        uint32_t n_ovf = 0, n64 = 0, n58 = 0, n28 = 0;
+        binom_column(A.max_deg, qA, col, n_ovf, n64, n58, n28);
+        for (uint64_t r = 0; r < A.n; ++r) {
+            const uint64_t d = A.h_ptr[r + 1] - A.h_ptr[r];
+            if (d >= n_ovf) return set_error(BC_E_OVERFLOW, "count exceeds 128 bits");
+            by_rank[r] = bc_u128{(uint64_t)col[d], (uint64_t)(col[d] >> 64)};
+        }
+    } else {
+        std::vector<JobSpec> sp{JobSpec{g, p, q, side, 0, 0, false, opts_deadline(opts)}};
+        sp[0].pv_out = by_rank.data();
+        std::vector<bc_u128> res;
+        std::vector<bc_status> ist;
+        bc_status s = run_jobs(sp, opts, res, ist, nullptr);
+        if (s != BC_OK) return s;
+        if (ist[0] != BC_OK) return ist[0];
+    }
+    for (uint64_t x = 0; x < A.n; ++x) counts[x] = by_rank[A.rank_of[x]];
+    return BC_OK;
+}
+
 extern "C" bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const uint32_t *q, size_t n,
                                     const bc_opts *opts, bc_u128 *out, bc_status *item_status, bc_stats *st)
 {
@@ -1855,6 +1919,28 @@ extern "C" bc_status bc_tune_batch(const bc_graph *const *graphs, const uint32_t
                 cur = c;
             }
         }
+    }
+    // The sample need not stand for the whole batch (it has fewer tasks per
+    // wave, and the automatic chunk size follows that count): the choice is
+    // kept only if it also beats the base schedule over all the items.
+    bool changed = false;
+    for (const Knob &kn : knobs) changed = changed || cur.*kn.field != b.*kn.field;
+    if (changed && sg.size() < n) {
+        std::vector<bc_u128> aout(n);
+        std::vector<bc_status> ast(n);
+        auto timed_all = [&](const bc_opts &c, double *t) -> bc_status {
+            const uint64_t t0 = bcint::steady_ns();
+            bc_status s = bc_count_batch(graphs, p, q, n, &c, aout.data(), ast.data(), nullptr);
+            if (s != BC_OK) return s;
+            *t = (double)(bcint::steady_ns() - t0);
+            for (bc_status x : ast)
+                if (x != BC_OK && b.timeout_ms) *t += (double)b.timeout_ms * 1e6;
+            return BC_OK;
+        };
+        double t_base = 0, t_cur = 0;
+        if (bc_status s = timed_all(b, &t_base)) return s;
+        if (bc_status s = timed_all(cur, &t_cur)) return s;
+        if (t_cur >= t_base) cur = b;
     }
     *tuned = cur;
     return BC_OK;

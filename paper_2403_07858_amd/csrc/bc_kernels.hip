@@ -2522,6 +2522,21 @@ constexpr uint32_t kSetLevels = 33;       // DFS levels (p_A <= 32)
 // HYBRID: the 64 lanes take 64 siblings at a time (Section IV's BFS over
 // siblings); otherwise the siblings are visited one at a time and the lanes
 // share each intersection (the pure DFS the paper's ablation compares with).
+// Adds v to vertex x's per-vertex count (two 64-bit atomics; the carry out of
+// the low word goes into the high one).  A count never exceeds the query's
+// total, which the result slot checks for overflow.
+__device__ __forceinline__ void pv_add(uint64_t *pv, uint32_t x, u128 v)
+{
+    unsigned long long *c = (unsigned long long *)(pv + 2ull * x);
+    const uint64_t lo = (uint64_t)v;
+    uint64_t hi = (uint64_t)(v >> 64);
+    if (lo) {
+        const unsigned long long old = atomicAdd(&c[0], (unsigned long long)lo);
+        if ((uint64_t)old + lo < (uint64_t)old) hi += 1;
+    }
+    if (hi) atomicAdd(&c[1], (unsigned long long)hi);
+}
+
 template <uint32_t MODE, bool HYBRID>
 __device__ void run_set_task(const Job &jb, const SetRoot &rt, uint32_t i, const uint32_t *ids, Arena ar,
                              uint64_t *stk, Acc &acc, Counters &ct, bool instrument, bool *cap_fail, bool *timed_out)
@@ -2538,6 +2553,19 @@ __device__ void run_set_task(const Job &jb, const SetRoot &rt, uint32_t i, const
     uint32_t m = set_intersect<MODE>(jb, nullptr, mu, true, u, cid[i], S, &bits);
     if (instrument) ct.filter_words += mu;
     if (bits < q) return;
+    if (pA == 2) {
+        // only with per-vertex counts (the candidate pass sums these leaves):
+        // L = {u, c_i} holds C(|S|, q) bicliques
+        if (jb.pv && ln == 0) {
+            if (bits >= jb.n_ovf) {
+                acc.ovf = true;
+            } else {
+                pv_add(jb.pv, u, jb.binom[bits]);
+                pv_add(jb.pv, cid[i], jb.binom[bits]);
+            }
+        }
+        return;
+    }
     // Saved per level d while a child is explored (wave-private LDS stack):
     // stk[8d] = S, [8d+1] = its element count, [8d+2] = kept list, [8d+3] =
     // cursor << 32 | kept count, [8d+4] = candidates, [8d+5] = their number,
@@ -2558,11 +2586,34 @@ __device__ void run_set_task(const Job &jb, const SetRoot &rt, uint32_t i, const
             if (d + 1 == pA) {
                 // leaves: every candidate c of this node adds C(|S n N(c)|, q)
                 if (HYBRID) {
+                    u128 node = 0;   // per-vertex counts: the node's leaves, for its members
                     for (uint32_t b0 = 0; b0 < nc; b0 += kWaveSize) {
                         const uint32_t b = b0 + ln;
                         if (b < nc) {
                             const uint32_t n = set_count<MODE>(jb, S, m, C[b]);
-                            if (n >= q) leaf_add(acc, jb.binom, jb.n_ovf, n);
+                            if (n >= q) {
+                                leaf_add(acc, jb.binom, jb.n_ovf, n);
+                                if (jb.pv && n < jb.n_ovf) {
+                                    pv_add(jb.pv, C[b], jb.binom[n]);
+                                    acc.ovf |= __builtin_add_overflow(node, jb.binom[n], &node);
+                                }
+                            }
+                        }
+                    }
+                    if (jb.pv) {
+                        // the node's members: the root, c_i and the vertex each
+                        // level 2 .. d-1 descended into (its kept list's entry
+                        // before the saved cursor)
+                        bool o = false;
+                        const u128 tot = wave_sum_u128(node, &o);
+                        acc.ovf |= o;
+                        if (ln == 0 && tot != 0) {
+                            pv_add(jb.pv, u, tot);
+                            pv_add(jb.pv, cid[i], tot);
+                            for (uint32_t dd = 2; dd < d; ++dd) {
+                                const uint32_t *Kd = (const uint32_t *)(uintptr_t)stk[8 * dd + 2];
+                                pv_add(jb.pv, Kd[(uint32_t)(stk[8 * dd + 3] >> 32) - 1], tot);
+                            }
                         }
                     }
                 } else {
