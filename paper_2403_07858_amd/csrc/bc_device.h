@@ -105,6 +105,7 @@ enum : unsigned {
 
 constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;
+constexpr uint32_t kTripleRows = 96;   // nodes up to this many rows finish their last three levels at once
 constexpr int kBlockThreads = kWaveSize * kWavesPerBlock;
 constexpr int kSortCap = 4096;          // candidates sorted in LDS up to this many
 constexpr int kRbWaves = 16;            // waves per block of the fused per-root kernel

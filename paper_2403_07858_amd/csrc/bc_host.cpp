@@ -1483,8 +1483,10 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         // (k / 2 + 1), then one block per DFS level 2 .. pA-2, each at most
         // (k - 1) rows of at most W1 words
         // (p_A >= 5: plus the pair rows of one small node's three-level sum,
-        // at most 96*95/2 rows of at most 4 words and their u32 indices)
-        uint64_t need = 10ull * pl.w1 + pl.k / 2 + 1 + (pA >= 5 ? 4560ull * 4 + 2281 : 0) +
+        // at most kTripleRows (kTripleRows - 1) / 2 rows of at most 4 words
+        // and their u32 indices)
+        const uint64_t pairs3 = (uint64_t)bcdev::kTripleRows * (bcdev::kTripleRows - 1) / 2;
+        uint64_t need = 10ull * pl.w1 + pl.k / 2 + 1 + (pA >= 5 ? pairs3 * 4 + (pairs3 + 1) / 2 : 0) +
                         (pA >= 4 ? (uint64_t)(pA - 3) * (pl.k - 1) * pl.w1 : 0) + 8;
         slab_need = std::max(slab_need, need);
     }
@@ -2333,7 +2335,8 @@ uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q, uint3
         if (pA < 3) continue;
         const double k = (double)std::min<uint64_t>(A.n ? A.n - 1 : 0, A.max_wedges);
         const double w1 = (double)((A.max_deg + 63) / 64);
-        const double need = 10 * w1 + k / 2 + 1 + (pA >= 5 ? 20521.0 : 0.0) +
+        const double pairs3 = (double)bcdev::kTripleRows * (bcdev::kTripleRows - 1) / 2;
+        const double need = 10 * w1 + k / 2 + 1 + (pA >= 5 ? pairs3 * 4 + pairs3 / 2 + 1 : 0.0) +
                             (pA >= 4 ? (double)(pA - 3) * std::max(0.0, k - 1) * w1 : 0.0) + 8;
         const double slab = std::min((double)(8ull << 30), (double)waves * need * 8);
         const uint64_t ring = pA >= 5 ? (64ull << 20) + 64 : 0;

@@ -32,7 +32,6 @@ constexpr uint32_t kTileWords = 4;            // widest row (64-bit words) of th
 constexpr uint32_t kTableLen = 64 * kTileWords + 4;   // per-wave LDS copy of C(n, q), n < kTableLen
 constexpr uint32_t kStackWords = 128;         // DFS stack at the start of each wave's LDS
 constexpr uint32_t kFilterDepth = 4;          // 64-row chunks loaded at once by the level-2 filter
-constexpr uint32_t kTripleRows = 96;          // nodes up to this many rows finish their last three levels at once
 
 
 uint32_t max_lds_words_per_wave() { return kLdsWordsPerWave; }
