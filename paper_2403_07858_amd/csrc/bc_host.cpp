@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cstddef>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -2346,6 +2347,19 @@ uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q, uint3
 }
 
 int graph_device(const bc_graph *g) { return g->device; }
+
+double query_cost(const bc_graph *g, uint32_t p, uint32_t q)
+{
+    double best = 0;
+    for (int a = 0; a < 2; ++a) {
+        const double pA = a == 0 ? p : q, qA = a == 0 ? q : p;
+        // wedges through the other side's vertices: what the candidate pass scans
+        const double c = (g->side[1 - a].deg_pairs + 1.0) * std::pow(4.0, std::max(0.0, pA - 2)) /
+                         std::pow(2.0, std::max(0.0, std::min(qA, 12.0) - 2));
+        best = a == 0 ? c : std::min(best, c);
+    }
+    return best;
+}
 
 }  // namespace bcint
 

@@ -26,6 +26,10 @@ bc_status count_queries(const Query *qs, size_t n, const bc_opts *opts, bc_u128 
 uint64_t estimate_scratch_bytes(const bc_graph *g, uint32_t p, uint32_t q, uint32_t waves_per_cu);
 
 int graph_device(const bc_graph *g);
+// Relative time of one (p,q) count on g, from the graph alone (no device
+// work): the wedges the candidate pass scans for the cheaper anchor, times 4
+// per level of L beyond two and halved per common neighbour asked beyond two.
+double query_cost(const bc_graph *g, uint32_t p, uint32_t q);
 
 // What the serving scheduler needs from the device side.  The library uses
 // hip_server_backend(); the scheduler itself touches no device API, so it can
@@ -41,6 +45,9 @@ struct ServerBackend {
     void (*stream_destroy)(void *stream);
     // default memory budget: half of the device memory free after the caches are trimmed
     uint64_t (*default_budget)();
+    // relative time of one count, known before any device work: the queue is
+    // served cheapest first (NULL: newest first)
+    double (*cost)(const bc_graph *g, uint32_t p, uint32_t q);
 };
 
 const ServerBackend *hip_server_backend();

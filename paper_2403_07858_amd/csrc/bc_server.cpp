@@ -12,6 +12,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -26,6 +27,7 @@ struct Ticket {
     uint32_t gid, p, q;
     uint64_t deadline_ns;
     uint64_t est_bytes;
+    double cost;   // the backend's relative time of the count
     uint64_t t_submit, t_start, t_done;
     bc_status status;
     bc_u128 value;
@@ -117,17 +119,32 @@ void worker_main(bc_server *s)
                         ++it;
                     }
                 }
-                // admit newest first while the memory budget allows: when
-                // queries arrive faster than they can be answered, taking the
-                // oldest would start only queries with little time left, so
-                // every query would expire; the newest have their whole
-                // deadline ahead of them
-                while (!s->pending.empty() && batch.size() < max_batch) {
-                    Ticket &t = s->tickets[s->pending.back()];
-                    if (s->inflight_bytes + batch_bytes + t.est_bytes > s->opts.memory_budget_bytes) break;
-                    batch_bytes += t.est_bytes;
-                    batch.push_back(s->pending.back());
-                    s->pending.pop_back();
+                // admit the cheapest first (the backend's cost), newest first
+                // among equals, while the memory budget allows: when queries
+                // arrive faster than they can be answered, the cheap ones are
+                // those that can still finish before their deadlines, and the
+                // oldest have the least time left.  Only the newest 4096
+                // pending queries are looked at.
+                if (!s->pending.empty()) {
+                    const size_t n = s->pending.size(), lo = n > 4096 ? n - 4096 : 0;
+                    std::vector<std::pair<double, size_t>> order;
+                    order.reserve(n - lo);
+                    for (size_t i = lo; i < n; ++i) order.push_back({s->tickets[s->pending[i]].cost, i});
+                    std::sort(order.begin(), order.end(), [](const std::pair<double, size_t> &a,
+                                                             const std::pair<double, size_t> &b) {
+                        return a.first != b.first ? a.first < b.first : a.second > b.second;
+                    });
+                    std::vector<size_t> taken;
+                    for (const auto &c : order) {
+                        if (batch.size() >= max_batch) break;
+                        const Ticket &t = s->tickets[s->pending[c.second]];
+                        if (s->inflight_bytes + batch_bytes + t.est_bytes > s->opts.memory_budget_bytes) continue;
+                        batch_bytes += t.est_bytes;
+                        batch.push_back(s->pending[c.second]);
+                        taken.push_back(c.second);
+                    }
+                    std::sort(taken.begin(), taken.end(), std::greater<size_t>());
+                    for (size_t i : taken) s->pending.erase(s->pending.begin() + (std::ptrdiff_t)i);
                 }
                 if (!batch.empty()) break;
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
@@ -236,6 +253,7 @@ extern "C" bc_status bc_server_submit(bc_server *s, uint32_t graph_id, uint32_t 
     t.q = q;
     t.deadline_ns = deadline_ns;
     t.est_bytes = s->be->estimate(s->graphs[graph_id], p, q, worker_waves(s));
+    t.cost = s->be->cost ? s->be->cost(s->graphs[graph_id], p, q) : 0.0;
     t.t_submit = bcint::steady_ns();
     t.done = false;
     if (t.est_bytes > s->opts.memory_budget_bytes || s->pending.size() >= s->opts.max_pending) {

@@ -32,6 +32,7 @@ uint64_t hip_default_budget()
 const bcint::ServerBackend kHipBackend = {
     bcint::count_queries, bcint::estimate_scratch_bytes, bcint::graph_device,
     hip_stream_create,    hip_stream_destroy,            hip_default_budget,
+    bcint::query_cost,
 };
 
 }  // namespace

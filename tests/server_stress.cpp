@@ -64,9 +64,11 @@ void fake_stream_destroy(void *s)
     delete (int *)s;
 }
 uint64_t fake_budget() { return 1ull << 20; }
+double fake_cost(const bc_graph *, uint32_t p, uint32_t q) { return (double)(p * q); }
 
 const bcint::ServerBackend kFake = {fake_count,         fake_estimate,       fake_device,
-                                    fake_stream_create, fake_stream_destroy, fake_budget};
+                                    fake_stream_create, fake_stream_destroy, fake_budget,
+                                    fake_cost};
 
 }  // namespace
 
