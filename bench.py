@@ -591,7 +591,8 @@ def run_ablation(args):
       global-set path, the binary-search (NB) comparator on sorted id
       lists, pure DFS on the global sets (NH), Border + HTB.
     - BCPar (Algorithm 3) on a 200k-edge graph of the same shape: the groups'
-      counts add up to the whole count; groups, largest closure, time."""
+      counts add up to the whole count; groups, largest closure, time.
+    - Per-vertex counts against the plain count of the same query."""
     import torch
 
     from paper_2403_07858_amd import bc, graphgen as gg
@@ -658,9 +659,38 @@ def run_ablation(args):
                          "status": "done" if c is not None else "capped", "count": None if c is None else str(c),
                          "ms_total": ms, "ms_enumerate": me})
             log(f"[ablation] ({p},{q}) ranks [{lo},{hi}) {name}: total {ms} ms, enumeration {me} ms")
+    # per-vertex counts (the output set of Algorithm 1 as membership counts):
+    # their time against the plain count of the same query
+    Gd = graphs["degree"]
+    for p, q, side in ((2, 3, bc.BC_ANCHOR_U), (2, 4, bc.BC_ANCHOR_U), (3, 2, bc.BC_ANCHOR_V)):
+        c, st = bc.bc_count(Gd, p, q, with_stats=True, stream=stream, anchor=side)
+        t0 = time.perf_counter()
+        try:
+            pv = bc.bc_count_per_vertex(Gd, p, q, side, stream=stream, timeout_ms=cap_ms)
+            ms = (time.perf_counter() - t0) * 1e3
+            assert sum(pv) == (p if side == bc.BC_ANCHOR_U else q) * c
+            status = "done"
+        except bc.BCError as e:
+            if e.status != bc.BC_E_TIMEOUT:
+                raise
+            ms, status = None, "capped"
+        rows.append({"scope": "graph", "variant": f"per-vertex counts, side {'UV'[side]}", "p": p, "q": q,
+                     "status": status, "count": str(c), "ms_total": ms, "count_ms_total": st["ms_total"]})
+        log(f"[ablation] ({p},{q}) per-vertex side {'UV'[side]}: {status} {ms} ms (count alone {st['ms_total']:.1f} ms)")
     # BCPar on a smaller graph of the same shape
     gs = gg.chung_lu_bipartite(10_000, 5_000, 200_000, 2.1, 2.1, 1000, 1000, seed=5)
     Gs = bc.build_graph(gs, stream=stream)
+    for p, q, side in ((4, 4, bc.BC_ANCHOR_U), (4, 4, bc.BC_ANCHOR_V)):
+        c, st = bc.bc_count(Gs, p, q, with_stats=True, stream=stream, anchor=side)
+        t0 = time.perf_counter()
+        pv = bc.bc_count_per_vertex(Gs, p, q, side, stream=stream)
+        ms = (time.perf_counter() - t0) * 1e3
+        assert sum(pv) == 4 * c
+        rows.append({"scope": "graph 10k x 5k, 200k edges", "variant": f"per-vertex counts, side {'UV'[side]}",
+                     "p": p, "q": q, "status": "done", "count": str(c), "ms_total": ms,
+                     "count_ms_total": st["ms_total"]})
+        log(f"[ablation] ({p},{q}) 200k-edge graph per-vertex side {'UV'[side]}: {ms:.1f} ms "
+            f"(count alone {st['ms_total']:.1f} ms)")
     for p, q in queries:
         want, st = bc.bc_count(Gs, p, q, with_stats=True, stream=stream)
         anchor = st["anchor"]
