@@ -92,6 +92,10 @@ def test_null_and_range_arguments(bc):
     assert lib.bc_graph_info(None, None, None, None) == bc.BC_E_INVALID_ARG
     lib.bc_free(None)  # NULL is ignored
     assert out.lo == 0 and out.hi == 0
+    counts = (bc.bc_u128 * 4)()
+    assert lib.bc_count_per_vertex(None, 2, 2, 0, None, counts) == bc.BC_E_INVALID_ARG
+    assert lib.bc_count_noalloc(None, 2, 2, None, ctypes.byref(out)) == bc.BC_E_INVALID_ARG
+    assert all(c.lo == 0 and c.hi == 0 for c in counts)
 
 
 def test_tune_batch_argument_errors(bc):
