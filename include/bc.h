@@ -260,10 +260,12 @@ bc_status bc_count_batch(const bc_graph *const *graphs, const uint32_t *p, const
  * hold x (in L for side U, in R for side V).  counts (host, one entry per
  * vertex of that side, indexed by the caller's vertex id) receives them;
  * their sum is p (side U) or q (side V) times bc_count.  The search runs with
- * `side` as the anchor on the global-set path, which visits every leaf with
- * its members known: a leaf's C(n, q_A) bicliques are added to each of its
- * p_A members (p_A = 1 is the closed form C(d(x), q_A)).  opts->sets picks
- * HTB (default) or sorted lists; pure_dfs is ignored.  Device scratch of 16
+ * `side` as the anchor: a leaf's C(n, q_A) bicliques are added to each of its
+ * p_A members.  With p_A = 2 the candidate pass does it as it counts each
+ * root's candidates; deeper searches run on the global-set path, which
+ * visits every leaf with its members known; p_A = 1 is the closed form
+ * C(d(x), q_A).  opts->sets picks HTB (default) or sorted lists; pure_dfs is
+ * ignored.  Device scratch of 16
  * bytes per vertex of the side comes on top of the count's.  Errors as for
  * bc_count; on error counts is untouched.
  */

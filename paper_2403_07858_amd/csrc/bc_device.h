@@ -161,7 +161,7 @@ hipError_t launch_cand_count(const Job *jobs, const uint64_t *job_root_prefix, u
 hipError_t launch_root_build(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
                              uint64_t total_roots, RootScratch scratch, uint64_t *pool, uint64_t pool_cap,
                              uint32_t n_blocks, unsigned long long *counters, uint32_t *out_k, uint64_t *out_off,
-                             Slot *slots, hipStream_t stream);
+                             Slot *slots, bool per_vertex, hipStream_t stream);
 hipError_t launch_rows_build(const Job *jobs, const ActiveRoot *roots, uint32_t n_roots,
                              uint64_t *pool, RootScratch scratch, uint32_t n_blocks,
                              unsigned long long *queue, Slot *slots, hipStream_t stream);

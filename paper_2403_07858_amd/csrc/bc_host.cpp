@@ -1186,6 +1186,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
                     sj.root_hi = (uint32_t)std::min<uint64_t>(c + kSampleChunk, jobs[j].root_hi);
                     sj.pA = 2;
                     sj.slot = nj;
+                    sj.pv = nullptr;
                     sjobs.push_back(sj);
                     sowner.push_back((uint32_t)j);
                     sprefix.push_back(sprefix.back() + (sj.root_hi - sj.root_lo));
@@ -1208,7 +1209,7 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
                 std::min<uint64_t>(s_roots, rs_blocks),
                 std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
             BC_HIP(bcdev::launch_root_build(d_sj, d_sp, (uint32_t)sjobs.size(), s_roots, rs, d_spool, 1, s_blocks,
-                                            d_queue + 6, d_sk, d_soff, d_slots, st));
+                                            d_queue + 6, d_sk, d_soff, d_slots, false, st));
             std::vector<uint32_t> sk(s_roots);
             BC_HIP(hipMemcpyAsync(sk.data(), d_sk, s_roots * 4, hipMemcpyDeviceToHost, st));
             BC_HIP(hipStreamSynchronize(st));
@@ -1296,8 +1297,9 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
             const uint32_t fused_blocks = (uint32_t)std::min<uint64_t>(
                 std::min<uint64_t>(total_roots, rs_blocks),
                 std::max<uint64_t>(1, (uint64_t)ncu * std::min(waves_per_cu, 12u) / 12));
+            // per-vertex counts of p_A = 2 jobs are attributed by this pass
             BC_HIP(bcdev::launch_root_build(d_cjobs, d_rp, (uint32_t)cj.size(), total_roots, rs, d_pool_fused, pool_cap,
-                                            fused_blocks, d_queue + 4, d_k, d_off, d_slots, st));
+                                            fused_blocks, d_queue + 4, d_k, d_off, d_slots, any_pv, st));
             h_off.resize(total_roots);
             BC_HIP(hipMemcpyAsync(h_off.data(), d_off, total_roots * 8, hipMemcpyDeviceToHost, st));
         } else {
@@ -1375,9 +1377,10 @@ bc_status run_jobs_impl(const std::vector<JobSpec> &specs, const bc_opts *opts, 
         const std::vector<uint8_t> *mask = specs[hj.spec].root_mask;
         for (uint64_t r = root_prefix[c]; r < root_prefix[c + 1]; ++r) {
             cand_edges += h_k[r];
-            // per-vertex counts also take the p_A = 2 roots through the
-            // global-set path (the candidate pass sums their leaves unattributed)
-            if (hj.pA < (specs[hj.spec].pv_out ? 2u : 3u) || h_k[r] < hj.pA - 1) continue;
+            // per-vertex counts of p_A = 2 jobs: the fused candidate pass
+            // attributes their leaves; the two-kernel pass does not, so then
+            // their roots take the global-set path
+            if (hj.pA < (specs[hj.spec].pv_out && !fused ? 2u : 3u) || h_k[r] < hj.pA - 1) continue;
             uint32_t u = (uint32_t)(hj.root_lo + (r - root_prefix[c]));
             if (mask && !(*mask)[u]) continue;
             uint32_t w1 = (uint32_t)((A.h_ptr[u + 1] - A.h_ptr[u] + 63) / 64);

@@ -139,6 +139,21 @@ __device__ void wave_flush(Slot *slots, uint32_t slot, u128 acc, bool ovf,
 }
 
 // True once the device real-time clock has passed a nonzero deadline.
+// Adds v to vertex x's per-vertex count (two 64-bit atomics; the carry out of
+// the low word goes into the high one).  A count never exceeds the query's
+// total, which the result slot checks for overflow.
+__device__ __forceinline__ void pv_add(uint64_t *pv, uint32_t x, u128 v)
+{
+    unsigned long long *c = (unsigned long long *)(pv + 2ull * x);
+    const uint64_t lo = (uint64_t)v;
+    uint64_t hi = (uint64_t)(v >> 64);
+    if (lo) {
+        const unsigned long long old = atomicAdd(&c[0], (unsigned long long)lo);
+        if ((uint64_t)old + lo < (uint64_t)old) hi += 1;
+    }
+    if (hi) atomicAdd(&c[1], (unsigned long long)hi);
+}
+
 __device__ __forceinline__ bool past_deadline(uint64_t deadline)
 {
     if (deadline == 0) return false;
@@ -665,6 +680,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_wsum
     return before + inc - v;
 }
 
+// PV: per-vertex counts for p_A = 2 jobs that ask for them (each leaf {u, w}
+// adds its C(|N(u) n N(w)|, q_A) to w at once and, summed per wave, to u).
+template <bool PV>
 __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, const uint64_t *job_root_prefix,
                                                            uint32_t n_jobs, uint64_t total_roots, RootScratch sc,
                                                            uint64_t *pool, uint64_t pool_cap,
@@ -733,6 +751,7 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
         }
         const bool one = W1 == 1;
         const bool rows = jb.pA >= 3;
+        u128 rsum = 0;   // PV: this thread's part of the root's leaves
 
         // pass 1: insert every 2-hop vertex; one-word roots OR in the row bit,
         // wider ones count.  It gives up at the first insert that finds no
@@ -809,6 +828,12 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
                         if (rows) continue;
                         if (c >= jb.n_ovf) ovf = true;
                         else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                        if constexpr (PV) {
+                            if (jb.pv && c < jb.n_ovf) {
+                                pv_add(jb.pv, s_key[h] - 1u, jb.binom[c]);
+                                rsum += jb.binom[c];
+                            }
+                        }
                     }
                 }
                 uint32_t kk;
@@ -892,6 +917,12 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
                     if (rows) continue;
                     if (c >= jb.n_ovf) ovf = true;
                     else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                    if constexpr (PV) {
+                        if (jb.pv && c < jb.n_ovf) {
+                            pv_add(jb.pv, s_key[h] - 1u, jb.binom[c]);
+                            rsum += jb.binom[c];
+                        }
+                    }
                 }
             }
             uint32_t pos = block_excl_scan(mine, s_wsum, &k);
@@ -965,6 +996,12 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
                     } else {
                         if (c >= jb.n_ovf) ovf = true;
                         else ovf |= __builtin_add_overflow(acc, jb.binom[c], &acc);
+                        if constexpr (PV) {
+                            if (jb.pv && c < jb.n_ovf) {
+                                pv_add(jb.pv, w, jb.binom[c]);
+                                rsum += jb.binom[c];
+                            }
+                        }
                         atomicExch(&cnt[w], 0u);
                     }
                 } else {
@@ -999,6 +1036,15 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
                 for (uint32_t s = tid; s < k; s += kRbThreads) atomicExch(&cnt[cand_g[s]], 0u);
         }
         if (build && off == ~0ull && tid == 0) atomicOr(&slots[jb.slot].flags, FLAG_POOL);
+        if constexpr (PV) {
+            // the root's own count: its leaves summed per wave, one add per wave
+            if (jb.pv && jb.pA == 2) {
+                bool o = false;
+                const u128 t = wave_sum_u128(rsum, &o);
+                ovf |= o;
+                if (lane_id() == 0 && t != 0) pv_add(jb.pv, u, t);
+            }
+        }
         if (tid == 0) {
             out_k[item] = k;
             out_off[item] = build ? off : ~0ull;
@@ -1016,11 +1062,15 @@ __global__ __launch_bounds__(kRbThreads) void k_root_build(const Job *jobs, cons
 hipError_t launch_root_build(const Job *jobs, const uint64_t *job_root_prefix, uint32_t n_jobs,
                              uint64_t total_roots, RootScratch scratch, uint64_t *pool, uint64_t pool_cap,
                              uint32_t n_blocks, unsigned long long *counters, uint32_t *out_k, uint64_t *out_off,
-                             Slot *slots, hipStream_t stream)
+                             Slot *slots, bool per_vertex, hipStream_t stream)
 {
     if (total_roots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_root_build, dim3(n_blocks), dim3(kRbThreads), 0, stream, jobs, job_root_prefix, n_jobs,
-                       total_roots, scratch, pool, pool_cap, counters, out_k, out_off, slots);
+    if (per_vertex)
+        hipLaunchKernelGGL(k_root_build<true>, dim3(n_blocks), dim3(kRbThreads), 0, stream, jobs, job_root_prefix,
+                           n_jobs, total_roots, scratch, pool, pool_cap, counters, out_k, out_off, slots);
+    else
+        hipLaunchKernelGGL(k_root_build<false>, dim3(n_blocks), dim3(kRbThreads), 0, stream, jobs, job_root_prefix,
+                           n_jobs, total_roots, scratch, pool, pool_cap, counters, out_k, out_off, slots);
     return hipGetLastError();
 }
 
@@ -2521,21 +2571,6 @@ constexpr uint32_t kSetLevels = 33;       // DFS levels (p_A <= 32)
 // HYBRID: the 64 lanes take 64 siblings at a time (Section IV's BFS over
 // siblings); otherwise the siblings are visited one at a time and the lanes
 // share each intersection (the pure DFS the paper's ablation compares with).
-// Adds v to vertex x's per-vertex count (two 64-bit atomics; the carry out of
-// the low word goes into the high one).  A count never exceeds the query's
-// total, which the result slot checks for overflow.
-__device__ __forceinline__ void pv_add(uint64_t *pv, uint32_t x, u128 v)
-{
-    unsigned long long *c = (unsigned long long *)(pv + 2ull * x);
-    const uint64_t lo = (uint64_t)v;
-    uint64_t hi = (uint64_t)(v >> 64);
-    if (lo) {
-        const unsigned long long old = atomicAdd(&c[0], (unsigned long long)lo);
-        if ((uint64_t)old + lo < (uint64_t)old) hi += 1;
-    }
-    if (hi) atomicAdd(&c[1], (unsigned long long)hi);
-}
-
 template <uint32_t MODE, bool HYBRID>
 __device__ void run_set_task(const Job &jb, const SetRoot &rt, uint32_t i, const uint32_t *ids, Arena ar,
                              uint64_t *stk, Acc &acc, Counters &ct, bool instrument, bool *cap_fail, bool *timed_out)

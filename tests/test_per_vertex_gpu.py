@@ -43,14 +43,18 @@ def test_per_vertex_matches_oracle(bc, shape):
 
 
 def test_per_vertex_sorted_lists_and_closed_forms(bc):
-    # the sorted-list comparator gives the same counts; on K_{a,b} every vertex
-    # of a side has the same count
+    # the sorted-list comparator gives the same counts, and so does the
+    # two-kernel candidate pass (L of two vertices then takes the global-set
+    # path instead of the fused pass's attribution); on K_{a,b} every vertex of
+    # a side has the same count
     g = gg.chung_lu_bipartite(200, 150, 2000, 2.2, 2.2, 50, 50, seed=72)
     G = bc.build_graph(g)
-    for p, q in [(3, 3), (2, 4)]:
+    for p, q in [(3, 3), (2, 4), (2, 2)]:
         a = bc.bc_count_per_vertex(G, p, q, bc.BC_ANCHOR_U)
         b = bc.bc_count_per_vertex(G, p, q, bc.BC_ANCHOR_U, sets=bc.BC_SETS_SORTED)
-        assert a == b
+        c = bc.bc_count_per_vertex(G, p, q, bc.BC_ANCHOR_U, root_build=bc.BC_ROOT_BUILD_TWO_PASS)
+        assert a == b == c
+        assert a == oracle.count_per_vertex(g, p, q)[0]
     a_, b_ = 9, 7
     us = [u for u in range(a_) for _ in range(b_)]
     vs = [v for _ in range(a_) for v in range(b_)]
