@@ -85,6 +85,15 @@ def main():
     ap.add_argument("--c3", action="store_true",
                     help="20M-edge workload: (6,6) over cost-balanced root ranges, and a bitmap-width sweep")
     ap.add_argument("--ranges", type=int, default=16)
+    ap.add_argument("--range-workload", default="power_law_20m", choices=sorted(WORKLOADS),
+                    help="--c3: the graph whose roots are split into ranges")
+    ap.add_argument("--range-query", default="6,6", help="--c3: the (p,q) counted over root ranges")
+    ap.add_argument("--range-anchor", default="V", choices=("U", "V"), help="--c3: the side the ranges are of")
+    ap.add_argument("--range-calibrate", default="",
+                    help="--c3: a cheaper (p,q) timed over 4x as many fine ranges; the ranges are then cut at equal "
+                         "sums of its times instead of equal sums of d^2")
+    ap.add_argument("--range-budget-s", type=float, default=0.0,
+                    help="--c3: start no range after this many seconds (0 = no limit); the rest is reported not run")
     ap.add_argument("--range-cap-s", type=float, default=15.0)
     ap.add_argument("--bitmap-sweep", default="64,128,256,512,1024,0")
     ap.add_argument("--no-batch", action="store_true",
@@ -506,10 +515,11 @@ def run_batch(args):
 
 
 def run_c3(args):
-    """The 20M-edge power-law graph: (6,6) over 16 cost-balanced root ranges
-    of one anchor, each under a device time limit (completed and capped
-    ranges reported, nothing extrapolated), then the bitmap width swept at
-    (4,4): roots with more neighbours than W bits take the HTB path."""
+    """A deep query over cost-balanced root ranges of one anchor, each under a
+    device time limit (completed and capped ranges reported, nothing
+    extrapolated): by default (6,6) on the 20M-edge power-law graph with 16
+    ranges of V; then (with --bitmap-sweep) the bitmap width swept at (4,4):
+    roots with more neighbours than W bits take the HTB path."""
     import numpy as np
     import torch
 
@@ -517,35 +527,60 @@ def run_c3(args):
 
     log = _log
     t0 = time.time()
-    g = gg.power_law_20m()
+    gen_name, _ = WORKLOADS[args.range_workload]
+    g = getattr(gg, gen_name)()
     log(f"[c3] generated {g.n_edges} edges in {time.time() - t0:.1f}s")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     G = bc.build_graph(g, stream=stream)
-    # anchor V for (6,6) (the sampled rule's choice at p = q >= 5 on this graph);
+    (rp, rq), = parse_queries(args.range_query)
+    side = bc.BC_ANCHOR_U if args.range_anchor == "U" else bc.BC_ANCHOR_V
     # ranges of equal sum over roots of d^2 (a per-root cost proxy), by rank
-    dv = np.sort(g.degrees_v().astype(np.float64))   # ranks follow ascending degree
+    deg = g.degrees_u() if side == bc.BC_ANCHOR_U else g.degrees_v()
+    dv = np.sort(deg.astype(np.float64))   # ranks follow ascending degree
     cum = np.cumsum(dv * dv)
-    cuts = [0] + [int(np.searchsorted(cum, cum[-1] * i / args.ranges)) for i in range(1, args.ranges)] + [g.n_v]
+    n_side = len(dv)
+    cuts = [0] + [int(np.searchsorted(cum, cum[-1] * i / args.ranges)) for i in range(1, args.ranges)] + [n_side]
+    calib = []
+    if args.range_calibrate:
+        # time a cheaper query over 4x finer ranges of equal d^2 sums, then
+        # merge them into ranges of equal time: its per-root cost follows the
+        # deep query's far more closely than d^2 does
+        (cp, cq), = parse_queries(args.range_calibrate)
+        nf = 4 * args.ranges
+        fine = [0] + [int(np.searchsorted(cum, cum[-1] * i / nf)) for i in range(1, nf)] + [n_side]
+        bc.bc_count_roots(G, 2, 2, side, 0, n_side, stream=stream)   # first-launch costs off the clock
+        for lo, hi in zip(fine, fine[1:]):
+            _, st = bc.bc_count_roots(G, cp, cq, side, lo, hi, with_stats=True, stream=stream)
+            calib.append({"rank_lo": lo, "rank_hi": hi, "ms_enumerate": st["ms_enumerate"]})
+        ct = np.cumsum([c["ms_enumerate"] for c in calib])
+        log(f"[c3] calibration ({cp},{cq}) over {nf} ranges: {ct[-1]:.1f} ms of enumeration")
+        idx = [int(np.searchsorted(ct, ct[-1] * i / args.ranges)) for i in range(1, args.ranges)]
+        cuts = sorted({0, n_side} | {fine[min(k + 1, nf)] for k in idx})
     ranges = []
+    t_start = time.perf_counter()
     for lo, hi in zip(cuts, cuts[1:]):
+        if args.range_budget_s and time.perf_counter() - t_start > args.range_budget_s:
+            ranges.append({"rank_lo": lo, "rank_hi": hi, "status": "not run", "count": None, "seconds": 0.0})
+            continue
         t1 = time.perf_counter()
         try:
-            c, st = bc.bc_count_roots(G, 6, 6, bc.BC_ANCHOR_V, lo, hi, with_stats=True, stream=stream,
+            c, st = bc.bc_count_roots(G, rp, rq, side, lo, hi, with_stats=True, stream=stream,
                                       timeout_ms=int(args.range_cap_s * 1000))
             ranges.append({"rank_lo": lo, "rank_hi": hi, "status": "done", "count": str(c),
                            "seconds": time.perf_counter() - t1})
         except bc.BCError as e:
             ranges.append({"rank_lo": lo, "rank_hi": hi, "status": "capped" if e.status == bc.BC_E_TIMEOUT
                            else bc.bc_status_string(e.status), "count": None, "seconds": time.perf_counter() - t1})
-        log(f"[c3] (6,6) V ranks [{lo},{hi}): {ranges[-1]['status']} {ranges[-1]['seconds']:.1f}s")
+        log(f"[c3] ({rp},{rq}) {args.range_anchor} ranks [{lo},{hi}): {ranges[-1]['status']} "
+            f"{ranges[-1]['seconds']:.1f}s")
     done = [r for r in ranges if r["status"] == "done"]
     done_count = sum(int(r["count"]) for r in done)
     done_s = sum(r["seconds"] for r in done)
     sweep = []
     base = None
     cap_ms = int(args.range_cap_s * 1000)
-    for w in [int(x) for x in args.bitmap_sweep.split(",")]:
+    for w in [int(x) for x in args.bitmap_sweep.split(",") if x.strip()]:
         try:
             c, st = bc.bc_count(G, 4, 4, anchor=bc.BC_ANCHOR_U, bitmap_bits=w, with_stats=True, stream=stream,
                                 timeout_ms=cap_ms)
@@ -570,10 +605,15 @@ def run_c3(args):
         "metric": "bicliques counted/sec", "value": done_count / done_s if done_s else 0.0, "unit": "bicliques/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": done_s * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u128", "data": "synthetic",
-        "config": {"workload": "power_law_20m", "query": "(6,6) on V root ranges; (4,4) bitmap sweep",
+        "config": {"workload": args.range_workload,
+                   "query": f"({rp},{rq}) on {args.range_anchor} root ranges"
+                            + ("; (4,4) bitmap sweep" if sweep else ""),
                    "n_u": g.n_u, "n_v": g.n_v, "edges": g.n_edges, "sha256": g.manifest["sha256"],
                    "range_cap_s": args.range_cap_s},
-        "ranges": ranges, "ranges_done": len(done), "ranges_capped": len(ranges) - len(done),
+        "calibration": calib,
+        "ranges": ranges, "ranges_done": len(done),
+        "ranges_capped": sum(1 for r in ranges if r["status"] == "capped"),
+        "ranges_not_run": sum(1 for r in ranges if r["status"] == "not run"),
         "bitmap_sweep_44": sweep,
     }
     print(json.dumps(line), flush=True)
