@@ -514,6 +514,28 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def equal_weight_cuts(weights, n_ranges):
+    """Cut points 0 = c_0 <= c_1 <= ... <= c_n = len(weights) that split the
+    sequence into n_ranges consecutive ranges of about equal weight."""
+    import numpy as np
+    cum = np.cumsum(np.asarray(weights, dtype=np.float64))
+    n = len(cum)
+    if n == 0:
+        return [0] * (n_ranges + 1)
+    return [0] + [int(np.searchsorted(cum, cum[-1] * i / n_ranges)) for i in range(1, n_ranges)] + [n]
+
+
+def merge_cuts(fine, times, n_ranges):
+    """Merges the consecutive ranges [fine[k], fine[k + 1]) with measured times
+    into at most n_ranges ranges of about equal total time; returns strictly
+    increasing cut points from fine[0] to fine[-1], each one of fine's."""
+    import numpy as np
+    ct = np.cumsum(np.asarray(times, dtype=np.float64))
+    nf = len(times)
+    idx = [int(np.searchsorted(ct, ct[-1] * i / n_ranges)) for i in range(1, n_ranges)] if nf else []
+    return sorted({fine[0], fine[-1]} | {fine[min(k + 1, nf)] for k in idx})
+
+
 def run_c3(args):
     """A deep query over cost-balanced root ranges of one anchor, each under a
     device time limit (completed and capped ranges reported, nothing
@@ -538,25 +560,22 @@ def run_c3(args):
     # ranges of equal sum over roots of d^2 (a per-root cost proxy), by rank
     deg = g.degrees_u() if side == bc.BC_ANCHOR_U else g.degrees_v()
     dv = np.sort(deg.astype(np.float64))   # ranks follow ascending degree
-    cum = np.cumsum(dv * dv)
     n_side = len(dv)
-    cuts = [0] + [int(np.searchsorted(cum, cum[-1] * i / args.ranges)) for i in range(1, args.ranges)] + [n_side]
+    cuts = equal_weight_cuts(dv * dv, args.ranges)
     calib = []
     if args.range_calibrate:
         # time a cheaper query over 4x finer ranges of equal d^2 sums, then
         # merge them into ranges of equal time: its per-root cost follows the
         # deep query's far more closely than d^2 does
         (cp, cq), = parse_queries(args.range_calibrate)
-        nf = 4 * args.ranges
-        fine = [0] + [int(np.searchsorted(cum, cum[-1] * i / nf)) for i in range(1, nf)] + [n_side]
+        fine = equal_weight_cuts(dv * dv, 4 * args.ranges)
         bc.bc_count_roots(G, 2, 2, side, 0, n_side, stream=stream)   # first-launch costs off the clock
         for lo, hi in zip(fine, fine[1:]):
             _, st = bc.bc_count_roots(G, cp, cq, side, lo, hi, with_stats=True, stream=stream)
             calib.append({"rank_lo": lo, "rank_hi": hi, "ms_enumerate": st["ms_enumerate"]})
-        ct = np.cumsum([c["ms_enumerate"] for c in calib])
-        log(f"[c3] calibration ({cp},{cq}) over {nf} ranges: {ct[-1]:.1f} ms of enumeration")
-        idx = [int(np.searchsorted(ct, ct[-1] * i / args.ranges)) for i in range(1, args.ranges)]
-        cuts = sorted({0, n_side} | {fine[min(k + 1, nf)] for k in idx})
+        times = [c["ms_enumerate"] for c in calib]
+        log(f"[c3] calibration ({cp},{cq}) over {len(times)} ranges: {sum(times):.1f} ms of enumeration")
+        cuts = merge_cuts(fine, times, args.ranges)
     ranges = []
     t_start = time.perf_counter()
     for lo, hi in zip(cuts, cuts[1:]):
