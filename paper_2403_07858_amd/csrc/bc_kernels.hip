@@ -1315,7 +1315,7 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
 {
     const uint32_t ln = lane_id();
     const uint32_t r16 = ln & 15;
-    const uint32_t nb = (m + 15) >> 4;
+    const uint32_t nb = __builtin_amdgcn_readfirstlane((m + 15) >> 4);   // the group bounds below stay scalar
     const uint32_t sh = 16 * (ln >> 4);
     const int tb = (int)lds_addr(t32);   // t32[0] = C(0, q) = 0
     const v4i c0 = {tb, tb, tb, tb};
@@ -1332,27 +1332,31 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
             x[w] = row < m ? v : 0ull;
         }
     };
-    for (uint32_t J0 = 0; J0 < nb; J0 += G) {
-        // column blocks past the last one are zero rows and add nothing
+    // Column groups end at the last block: when G does not divide nb the
+    // first group starts below block 0.  Its blocks J < 0 are zero rows that
+    // meet no row block (row blocks I < 0 are skipped, and a row block I
+    // meets only the columns J >= I), so no product is spent past m.
+    const uint32_t part = nb % G;
+    for (int J0 = part ? (int)part - G : 0; J0 < (int)nb; J0 += G) {
         v4i ej[G][W];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             uint64_t x[W];
-            fetch(J0 + g, x);
+            fetch(J0 + g >= 0 ? (uint32_t)(J0 + g) : nb, x);   // block nb lies past m: zero rows
 #pragma unroll
             for (int w = 0; w < W; ++w) ej[g][w] = spread_bits<4>(x[w], ln);
         }
-        const uint32_t imax = min(J0 + G, nb);
         uint64_t s64 = 0;
-        // row blocks I < imax; the next block's words are fetched one step ahead
+        // row blocks up to the group's last (J0 + G - 1 <= nb - 1); the next
+        // block's words are fetched one step ahead
         uint64_t nx[W];
         fetch(0, nx);
         // row blocks before the group: every entry is above the diagonal
-        for (uint32_t I = 0; I < J0; ++I) {
+        for (int I = 0; I < J0; ++I) {
             v4i ei[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) ei[w] = spread1_lut(nx[w], sh);
-            fetch(I + 1, nx);
+            fetch((uint32_t)I + 1, nx);
             v4i d[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) d[g] = mfma_block<W>(ei, ej[g], c0);
@@ -1363,21 +1367,22 @@ __device__ void pair_sum_mfma(const uint64_t *blk, uint32_t stride, uint32_t m, 
                 for (int i = 0; i < 4; ++i) s += lds_load_u32((uint32_t)d[g][i]);
             s64 += s;
         }
-        // row blocks inside the group: blocks on and above the diagonal
-        for (uint32_t I = J0; I < imax; ++I) {
+        // row blocks inside the group: row block J0 + i meets the column
+        // blocks J0 + g with g >= i, and only g = i is a diagonal block
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (J0 + i < 0) continue;   // wave-uniform: blocks below 0 (first group only)
+            const uint32_t I = (uint32_t)(J0 + i);
             v4i ei[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) ei[w] = spread1_lut(nx[w], sh);
-            if (I + 1 < imax) fetch(I + 1, nx);
+            if (i + 1 < G) fetch(I + 1, nx);
             uint32_t s = 0;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const uint32_t J = J0 + g;
-                if (I > J) continue;   // wave-uniform
+            for (int g = i; g < G; ++g) {
                 const v4i d = mfma_block<W>(ei, ej[g], c0);
-                const bool diag = I == J;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) s += lds_load_u32((!diag || above[i]) ? (uint32_t)d[i] : (uint32_t)tb);
+                for (int k = 0; k < 4; ++k) s += lds_load_u32((g > i || above[k]) ? (uint32_t)d[k] : (uint32_t)tb);
             }
             s64 += s;
         }
@@ -1658,14 +1663,9 @@ __device__ __forceinline__ void count_pairs(Counters &ct, uint32_t m, uint32_t W
     const unsigned long long pr = (unsigned long long)m * (m - 1) / 2;
     ct.pairs += pr;
     ct.pair_words += pr * W;
-    if (G) {
-        const uint32_t nb = (m + 15) / 16;
-        unsigned long long blocks = 0;
-        for (uint32_t J0 = 0; J0 < nb; J0 += G) {
-            blocks += (unsigned long long)J0 * G;
-            for (uint32_t I = J0; I < min(J0 + G, nb); ++I) blocks += J0 + G - I;
-        }
-        ct.pair_slots += blocks * 256;
+    if (G) {   // one 16 x 16 product per block pair I <= J, whatever the group width
+        const unsigned long long nb = (m + 15) / 16;
+        ct.pair_slots += nb * (nb + 1) / 2 * 256;
         return;
     }
     for (uint32_t b0 = 0; b0 < m; b0 += kWaveSize)   // full tiles, then the folded diagonal tile
