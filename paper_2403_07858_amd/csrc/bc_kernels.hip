@@ -1601,6 +1601,20 @@ __device__ uint32_t filter_children(const uint64_t *blk, uint32_t stride, uint32
 {
     const uint32_t ln = lane_id();
     uint32_t out = 0;
+    if (W == 1) {   // one-word rows: row a read once, each AND computed once
+        const uint64_t ra = blk[a];
+        for (uint32_t b0 = a + 1; b0 < m; b0 += kWaveSize) {
+            const uint32_t b = b0 + ln;
+            const bool valid = b < m;
+            const uint64_t v = valid ? ra & blk[b] : 0ull;
+            const bool keep = valid && (uint32_t)__popcll(v) >= q;
+            const uint64_t mask = __ballot(keep);
+            if (keep) nblk[out + mbcnt64(mask)] = v;
+            out += (uint32_t)__popcll(mask);
+        }
+        wave_sync();
+        return out;
+    }
     for (uint32_t b0 = a + 1; b0 < m; b0 += kWaveSize) {
         const uint32_t b = b0 + ln;
         const bool valid = b < m;
