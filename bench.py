@@ -40,9 +40,9 @@ HBM_PEAK = 8.0e12
 # HBM bytes of one k_enumerate launch for (4,4) on the power-law 2M-edge graph,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by the same counter on a
 # 1 GiB device copy), valid only for the kernel source they were taken on.
-TRAFFIC_KERNEL_SHA256_PREFIX = "028dea8cafaad00f"
+TRAFFIC_KERNEL_SHA256_PREFIX = "d93191dce7218f63"
 TRAFFIC_WORKLOAD = "power_law_2m"
-TRAFFIC_BYTES_Q44 = (923047.625 * 2.0 + 1031960.5625 * 1.0) * 1024
+TRAFFIC_BYTES_Q44 = (923703.125 * 2.0 + 1033914.8125 * 1.0) * 1024
 
 WORKLOADS = {
     "power_law_2m": ("power_law_2m", [(4, 4), (4, 6), (6, 4), (5, 5)]),
