@@ -69,6 +69,33 @@ def test_closed_forms(bc):
         assert bc.bc_count(G, p, q) == math.comb(n, p) * math.comb(n - p, q)
 
 
+@pytest.mark.parametrize("a", [18, 33, 50, 66, 83, 100, 131])
+def test_leaf_block_sizes_complete(bc, a):
+    # K_{a,12} anchored on U: root rank r keeps a - 1 - r candidates, so the
+    # level-2 and level-3 blocks take every size from 1 to a - 2 (every
+    # residue of the 16-row blocks and of the column groups of the leaf sum)
+    b = 12
+    G = bc.build_graph(_complete(a, b))
+    for p, q in [(4, 4), (5, 5), (4, 12), (6, 3)]:
+        want = math.comb(a, p) * math.comb(b, q)
+        say("complete", a, b, p, q)
+        assert bc.bc_count(G, p, q, anchor=bc.BC_ANCHOR_U) == want, (a, p, q)
+        assert bc.bc_count(G, p, q) == want, (a, p, q)
+
+
+@pytest.mark.parametrize("n", [40, 65, 100])
+def test_leaf_block_sizes_crown(bc, n):
+    # crown graphs (K_{n,n} less a perfect matching): dense rows of one or two
+    # words, blocks of every size below n; count C(n, p) C(n - p, q)
+    crown = _graph_from_adj(n, n, [[j for j in range(n) if j != i] for i in range(n)])
+    G = bc.build_graph(crown)
+    for p, q in [(4, 4), (5, 5), (5, 3)]:
+        want = math.comb(n, p) * math.comb(n - p, q)
+        say("crown", n, p, q)
+        assert bc.bc_count(G, p, q, anchor=bc.BC_ANCHOR_U) == want, (n, p, q)
+        assert bc.bc_count(G, p, q, anchor=bc.BC_ANCHOR_V) == want, (n, p, q)
+
+
 def test_exact_beyond_64_bits_and_overflow(bc):
     # K_{3,80} at (1,32): 3 * C(80, 32) needs more than 64 bits.
     G = bc.build_graph(_complete(3, 80))
